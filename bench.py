@@ -1,0 +1,199 @@
+"""Benchmark: look-ahead LU at n = 32768 on one MI355X.
+
+One step = the whole hot path on one batch of synthetic input resident in HBM:
+  1. FP64 look-ahead LU (lu_factor) of a uniform[-1,1) n x n matrix
+     (restored from a pristine device copy first; the copy is outside the
+     factorization's event timing),
+  2. lu_solve with one uniform[-1,1) right-hand side,
+  3. lu_solve_ir in mixed precision (FP16 trailing GEMM, FP32 panel/TRSM, FP64
+     refinement) on the row-dominant matrix of the same size.
+`value` is the FP64 factorization rate 2/3 n^3 / t_factor (median over the
+timed steps, HIP events on the stream the factorization runs on).
+
+Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+"""
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "LU GFLOPS (2/3·n³/t) at n=32768, FP64 vs mixed+IR; % MFMA peak; IR time-to-solve"
+FP64_PEAK_TFLOPS = 78.6
+
+
+def cpu_baseline(budget_s=20.0):
+    """Time the CPU oracle on a bounded sample of the same workload."""
+    import numpy as np
+    import oracle
+    import synth
+    cores = min(16, len(os.sched_getaffinity(0)))
+    # calibrate on a small case, then pick n for ~budget_s of work (cubic scaling)
+    n0 = 768
+    A = synth.uniform(n0, seed=7)
+    t0 = time.perf_counter()
+    oracle.getrf(A, nthreads=cores)
+    t_small = time.perf_counter() - t0
+    n = int(n0 * (budget_s / max(t_small, 1e-3)) ** (1 / 3))
+    n = max(n0, min(n, 8192)) // 64 * 64
+    A = synth.uniform(n, seed=1)
+    t0 = time.perf_counter()
+    oracle.getrf(A, nthreads=cores)
+    t = time.perf_counter() - t0
+    return {"value": round((2.0 / 3.0) * n ** 3 / t / 1e9, 3), "unit": "GFLOP/s", "cores": cores,
+            "kind": "oracle",
+            "sample": "one FP64 partial-pivoting LU of a uniform[-1,1) %dx%d matrix (%.1f s)" % (n, n, t)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=32768)
+    ap.add_argument("--b", type=int, default=0)
+    ap.add_argument("--depth", type=int, default=-1)
+    ap.add_argument("--panel-cus", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ir", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only (the hot path is built and measured on a single MI355X); "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1804_07017_amd as lu
+    lu.load()
+    torch.cuda.set_device(0)
+    n = args.n
+    dev = "cuda"
+    g = torch.Generator(device=dev)
+    g.manual_seed(1)
+    print("bench: generating n=%d inputs" % n, file=sys.stderr, flush=True)
+    A0 = lu.colmajor(n)
+    A0.uniform_(-1.0, 1.0, generator=g)
+    A = lu.colmajor(n)
+    bvec = torch.empty(n, dtype=torch.float64, device=dev).uniform_(-1.0, 1.0, generator=g)
+    x = torch.empty(n, dtype=torch.float64, device=dev)
+    ipiv = torch.zeros(n, dtype=torch.int32, device=dev)
+    D = None
+    if not args.no_ir:
+        D = lu.colmajor(n)
+        D.uniform_(-1.0, 1.0, generator=g)
+        rowsum = D.abs().sum(dim=1)
+        D.diagonal().copy_(rowsum)
+        del rowsum
+        X = torch.empty(n, dtype=torch.float64, device=dev)
+    stream = torch.cuda.Stream()
+    sched = None
+    if args.b > 0 or args.depth >= 0 or args.panel_cus > 0:
+        sched = (args.b, args.depth if args.depth >= 0 else 1, args.panel_cus)
+    rc, used = lu.lu_schedule_default(n, lu.LU_FP64)
+    if sched is not None:
+        used = (sched[0] or used[0], sched[1], sched[2] or used[2])
+    torch.cuda.synchronize()
+
+    def step(rec):
+        with torch.cuda.stream(stream):
+            A.copy_(A0)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e2 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            r = lu.lu_factor_ex(A, ipiv, prec=lu.LU_FP64, sched=sched, stream=stream)
+            assert r == 0, r
+            e1.record(stream)
+            x.copy_(bvec)
+            r = lu.lu_solve_ex(A, ipiv, x, stream=stream)
+            assert r == 0, r
+            e2.record(stream)
+            ir = None
+            if D is not None:
+                stream.synchronize()
+                t0 = time.perf_counter()
+                st, it, res = lu.lu_solve_ir(D, bvec, X, prec=lu.LU_MIXED_FP16, max_iter=10, stream=stream)
+                stream.synchronize()
+                ir = (st, it, res, (time.perf_counter() - t0) * 1e3)
+        stream.synchronize()
+        rec.append((e0.elapsed_time(e1), e1.elapsed_time(e2), ir))
+
+    warm = []
+    for i in range(args.warmup):
+        print("bench: warmup step %d" % i, file=sys.stderr, flush=True)
+        step(warm)
+    rc, info = lu.lu_factor_info()
+    if rc != 0:
+        print("bench: factorization error %d" % rc, file=sys.stderr)
+        sys.exit(1)
+
+    lu.lu_k_timing(1)
+    recs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(recs)
+        print("bench: step %d factor %.1f ms solve %.2f ms ir %s" % (i, recs[-1][0], recs[-1][1], recs[-1][2]),
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lu.lu_k_timing(0)
+    rc_t, gemm_ms, gemm_flops, gemm_launches = lu.lu_k_timing_read()
+
+    # correctness of the last step: HPL residual of the FP64 solve (device GEMV in FP64)
+    with torch.no_grad():
+        A0r = A0.abs().sum(dim=1).max().item()
+        r = (A0 @ x - bvec).abs().max().item()
+        hpl = r / (2.0 ** -53 * (A0r * x.abs().max().item() + bvec.abs().max().item()) * n)
+
+    t_fact = statistics.median(r[0] for r in recs)
+    t_solve = statistics.median(r[1] for r in recs)
+    flops = (2.0 / 3.0) * n ** 3
+    gflops = flops / (t_fact * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": round(gflops, 1),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "FP64 look-ahead LU + 1-RHS solve of a uniform[-1,1) n=%d matrix; mixed FP16 LU "
+                               "+ FP64 refinement on the row-dominant n=%d matrix" % (n, n),
+                   "n": n, "b": used[0], "depth": used[1], "panel_cus": used[2]},
+        "fp64": {"t_factor_ms": round(t_fact, 3), "t_solve_ms": round(t_solve, 3),
+                 "tts_ms": round(t_fact + t_solve, 3), "pct_fp64_peak": round(100 * gflops / 1e3 / FP64_PEAK_TFLOPS, 2),
+                 "hpl_resid": hpl},
+    }
+    if D is not None:
+        irs = [r[2] for r in recs]
+        t_ir = statistics.median(i[3] for i in irs)
+        out["mixed_ir"] = {"status": irs[-1][0], "iters": irs[-1][1], "hpl_resid": irs[-1][2],
+                           "tts_ms": round(t_ir, 3),
+                           "speedup_vs_fp64_tts": round((t_fact + t_solve) / t_ir, 3),
+                           "effective_gflops": round(flops / (t_ir * 1e-3) / 1e9, 1)}
+    if rc_t == 0 and gemm_launches > 0:
+        ach = gemm_flops / (gemm_ms * 1e-3) / 1e12
+        out["roofline"] = {"bound": "mfma", "kernel": "gemm_nn_sub<double,16> (trailing update)",
+                           "achieved": round(ach, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": round(ach / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                           "launches": gemm_launches,
+                           "avg_launch_us": round(gemm_ms * 1e3 / gemm_launches, 2),
+                           "avg_launch_gflop": round(gemm_flops / gemm_launches / 1e9, 3)}
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,57 @@
+/*
+ * lu_plan.h -- the look-ahead schedule as an inspectable task list.
+ *
+ * The factorization is a DAG over elimination steps k = 0..N-1
+ * (N = ceil(n/b); the last panel has width n-(N-1)b when b does not divide n):
+ *   PANEL(j)        factor panel j: columns [jb, jb+w_j), rows >= jb
+ *                   (RL1 of LU_blk, Sec. 3.5), producing ipiv[jb..jb+w_j)
+ *   UPDATE(k,c0,c1) apply step k to columns [c0,c1): the interchanges of
+ *                   panel k, RL2 (U12 := trilu(A11)^-1 A12) and RL3
+ *                   (A22 -= A21 A12) (Sec. 3.4, 3.5)
+ *   LSWAP(k,0,kb)   apply the interchanges of panel k to the finished
+ *                   columns left of it (the left half of laswp, Sec. 3.4)
+ * A schedule places these tasks in a program order that is a valid
+ * sequential order of the algorithm (Listing 3 for depth 0, Listing 5 of
+ * Sec. 4 for depth 1, two panels ahead for depth 2) and assigns each to one
+ * of two streams: 0 = the update stream (the caller's stream), 1 = the panel
+ * stream.  Each task lists the earlier tasks of the OTHER stream it must wait
+ * for; these are derived mechanically from the column ranges and pivot
+ * blocks each task reads and writes, so concurrently runnable tasks touch
+ * disjoint data and every execution order the streams allow gives the
+ * result of the program order.
+ */
+#ifndef LU_MI355X_PLAN_H
+#define LU_MI355X_PLAN_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LU_TASK_PANEL  0
+#define LU_TASK_UPDATE 1
+#define LU_TASK_LSWAP  2
+
+#define LU_PLAN_MAX_WAIT 2
+
+typedef struct {
+    int kind;                   /* LU_TASK_*                                          */
+    int step;                   /* k (PANEL: the panel index j)                       */
+    int col_begin, col_end;     /* columns written, [col_begin, col_end)              */
+    int stream;                 /* 0 = update stream, 1 = panel stream                */
+    int nwait;                  /* cross-stream waits                                 */
+    int wait[LU_PLAN_MAX_WAIT]; /* indices of earlier tasks (other stream) to wait on */
+    int record;                 /* 1 if a later task waits on this one                */
+} lu_plan_task_t;
+
+/* Build the task list for an n x n factorization with block size b and
+ * look-ahead depth (0, 1 or 2) into out[0..max_tasks) (host memory).
+ * Pure host code: no GPU call.  Returns the number of tasks, or -1 n<0,
+ * -2 b<1, -3 depth not in {0,1,2}, -5 max_tasks too small (the return value
+ * is then -5 and nothing beyond max_tasks is written). */
+int lu_plan_build(int n, int b, int depth, lu_plan_task_t* out, int max_tasks);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LU_MI355X_PLAN_H */

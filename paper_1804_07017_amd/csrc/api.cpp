@@ -1,0 +1,587 @@
+// C ABI of the look-ahead LU library: argument checks, workspace, schedule
+// resolution and the executor that turns the task plan into launches on the
+// caller's stream (trailing updates) and the library's panel stream.
+//
+// Method (paper): the blocked right-looking LU of Sec. 3.5 (RL1-RL3), with
+// the row interchanges of LAPACK getrf (Sec. 3.4), reorganised with static
+// look-ahead (Sec. 4, Listing 5).  The panel kernel of step j runs on the
+// panel stream while the right part of the trailing update of the step before
+// runs on the caller's stream; the waits between the two streams come from
+// the plan (plan.cpp).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+
+#include "../../include/lu.h"
+#include "../../include/lu_kernels.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+#include "selector.hpp"
+#include "state.hpp"
+
+namespace lu {
+
+namespace {
+std::map<int, DeviceState*> g_states;
+
+// optional per-launch timing of the trailing GEMM
+struct GemmTiming {
+    bool on = false;
+    std::vector<hipEvent_t> ev;     // start/stop pairs
+    std::vector<double> flops;
+    size_t used = 0;                // pairs in use
+} g_timing;
+
+int timed_begin(hipStream_t st, int M, int N, int K, hipEvent_t* stop) {
+    *stop = nullptr;
+    if (!g_timing.on) return 0;
+    if (g_timing.used * 2 + 2 > g_timing.ev.size()) {
+        for (int i = 0; i < 2 * 256; ++i) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return LU_ERR_HIP;
+            g_timing.ev.push_back(e);
+        }
+    }
+    hipEvent_t start = g_timing.ev[2 * g_timing.used];
+    *stop = g_timing.ev[2 * g_timing.used + 1];
+    g_timing.flops.resize(g_timing.used + 1);
+    g_timing.flops[g_timing.used] = 2.0 * M * (double)N * K;
+    g_timing.used++;
+    return hipEventRecord(start, st) == hipSuccess ? 0 : LU_ERR_HIP;
+}
+constexpr int kEventRing = 1024;
+constexpr int kMaxCand = 256;       // max panel work-groups
+constexpr int kNB = 16;             // panel register block width (panel.hip)
+}  // namespace
+
+int ensure(Buffer& b, size_t bytes) {
+    if (bytes <= b.bytes && b.ptr) return 0;
+    if (b.ptr) {
+        if (hipDeviceSynchronize() != hipSuccess) return LU_ERR_HIP;
+        hipFree(b.ptr);
+        b.ptr = nullptr;
+        b.bytes = 0;
+    }
+    if (bytes == 0) return 0;
+    if (hipMalloc(&b.ptr, bytes) != hipSuccess) return LU_ERR_NOMEM;
+    b.bytes = bytes;
+    return 0;
+}
+
+void release(Buffer& b) {
+    if (b.ptr) hipFree(b.ptr);
+    b.ptr = nullptr;
+    b.bytes = 0;
+}
+
+DeviceState* device_state(int* err) {
+    *err = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) { *err = LU_ERR_HIP; return nullptr; }
+    auto it = g_states.find(dev);
+    if (it != g_states.end()) return it->second;
+    DeviceState* s = new DeviceState();
+    s->dev = dev;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) { *err = LU_ERR_HIP; delete s; return nullptr; }
+    s->num_cus = prop.multiProcessorCount;
+    int rate_khz = 0;
+    if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || rate_khz <= 0)
+        rate_khz = 100000;
+    s->spin_limit = (long long)rate_khz * 1000ll * 2;   // 2 seconds
+    if (const char* e = std::getenv("LU_DEBUG_BARRIER_SPIN")) {
+        long long v = std::atoll(e);
+        if (v > 0) s->spin_limit = v;                    // debug knob: tiny bound forces the timeout path
+    }
+    if (hipStreamCreateWithFlags(&s->panel_stream, hipStreamNonBlocking) != hipSuccess) {
+        *err = LU_ERR_HIP; delete s; return nullptr;
+    }
+    s->events.resize(kEventRing);
+    for (auto& e : s->events)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) { *err = LU_ERR_HIP; return nullptr; }
+    if (hipMalloc(&s->sync, 8 * sizeof(unsigned)) != hipSuccess) { *err = LU_ERR_NOMEM; return nullptr; }
+    if (hipMemset(s->sync, 0, 8 * sizeof(unsigned)) != hipSuccess) { *err = LU_ERR_HIP; return nullptr; }
+    if (hipMalloc(&s->info, 4 * sizeof(int)) != hipSuccess) { *err = LU_ERR_NOMEM; return nullptr; }
+    if (hipMemset(s->info, 0, 4 * sizeof(int)) != hipSuccess) { *err = LU_ERR_HIP; return nullptr; }
+    // candidate area sized for double and the maximum work-group count
+    size_t cand = 2 * kMaxCand * sizeof(double) + 2 * kMaxCand * sizeof(int) + 2 * kMaxCand * kNB * sizeof(double) +
+                  2 * kNB * sizeof(double) + 256;
+    if (ensure(s->cand, cand)) { *err = LU_ERR_NOMEM; return nullptr; }
+    g_states[dev] = s;
+    return s;
+}
+
+void release_all() {
+    for (auto& kv : g_states) {
+        DeviceState* s = kv.second;
+        hipSetDevice(s->dev);
+        hipDeviceSynchronize();
+        for (auto& e : s->events) hipEventDestroy(e);
+        if (s->panel_stream) hipStreamDestroy(s->panel_stream);
+        if (s->sync) hipFree(s->sync);
+        if (s->info) hipFree(s->info);
+        Buffer* bufs[] = {&s->cand, &s->moves, &s->lh, &s->uh, &s->rs, &s->cs, &s->solve_moves, &s->flags,
+                          &s->partial, &s->ir_r, &s->ir_x32, &s->ir_a32, &s->ir_a64, &s->ir_norms, &s->ir_ipiv,
+                          &s->ir_b};
+        for (Buffer* b : bufs) release(*b);
+        delete s;
+    }
+    g_states.clear();
+}
+
+int panel_wgs_for(const DeviceState& s, int m, int panel_cus) {
+    const int per = panel_max_rows_per_wg();
+    int need = (m + per - 1) / per;
+    int wgs = std::max(need, std::max(1, panel_cus));
+    // at least one row block per work-group is useful; never more groups than rows/64
+    int useful = std::max(need, (m + 255) / 256);
+    wgs = std::min(wgs, std::max(need, useful));
+    if (wgs > kMaxCand || wgs > s.num_cus) return -1;
+    return wgs;
+}
+
+namespace {
+
+// ---------------------------------------------------------------- schedule
+bool valid_b(int b) { return b == 32 || b == 64 || b == 128 || b == 256 || b == 512; }
+
+int env_int(const char* name, int dflt) {
+    const char* e = std::getenv(name);
+    if (!e || !*e) return dflt;
+    return std::atoi(e);
+}
+
+void resolve_schedule(int n, lu_precision_t prec, const lu_schedule_t* req, lu_schedule_t* out) {
+    lu_schedule_t s = {256, 1, 16};
+    lu_schedule_t sel;
+    const bool sel_on = selector_enabled() && selector_predict(n, (int)prec, &sel) == 0;
+    if (sel_on) s = sel;
+    int e;
+    if ((e = env_int("LU_B", 0)) > 0 && valid_b(e)) s.b = e;
+    if ((e = env_int("LU_DEPTH", -1)) >= 0 && e <= 2) s.depth = e;
+    if ((e = env_int("LU_PANEL_CUS", 0)) > 0 && e <= 256) s.panel_cus = e;
+    if (req) {
+        if (req->b > 0) s.b = req->b;
+        if (req->depth >= 0 && req->depth <= 2 && (req->b > 0 || req->depth > 0 || req->panel_cus > 0)) {
+            // depth 0 is a legal explicit value only when the caller set some field
+            s.depth = req->depth;
+        }
+        if (req->panel_cus > 0) s.panel_cus = req->panel_cus;
+    }
+    *out = s;
+}
+
+const std::vector<PlanTask>* get_plan(DeviceState* s, int n, int b, int depth) {
+    const long long key = ((long long)n << 16) ^ ((long long)b << 4) ^ depth;
+    auto it = s->plans.find(key);
+    if (it != s->plans.end()) return &it->second;
+    if (s->plans.size() > 64) s->plans.clear();
+    std::vector<PlanTask> v;
+    if (build_plan(n, b, depth, v) < 0) return nullptr;
+    return &(s->plans[key] = std::move(v));
+}
+
+// ---------------------------------------------------------------- executor
+struct HalfNone {};
+
+template <typename T> struct CandPtrs {
+    T* val; int* idx; T* rows; T* diag;
+};
+
+template <typename T>
+CandPtrs<T> cand_ptrs(DeviceState* s) {
+    char* base = reinterpret_cast<char*>(s->cand.ptr);
+    CandPtrs<T> c;
+    c.val = reinterpret_cast<T*>(base);
+    c.idx = reinterpret_cast<int*>(base + 2 * kMaxCand * sizeof(double));
+    c.rows = reinterpret_cast<T*>(base + 2 * kMaxCand * sizeof(double) + 2 * kMaxCand * sizeof(int));
+    c.diag = reinterpret_cast<T*>(base + 2 * kMaxCand * sizeof(double) + 2 * kMaxCand * sizeof(int) +
+                                  2 * kMaxCand * kNB * sizeof(double));
+    return c;
+}
+
+template <typename T>
+int run_panel(DeviceState* s, T* A, long long lda, int n, int j0, int w, int* ipiv, int* info, int* moves,
+              int wgs_req, hipStream_t st) {
+    PanelArgs<T> pa;
+    const int m = n - j0;
+    pa.A = A + j0 + (long long)j0 * lda;
+    pa.lda = (int)lda;
+    pa.m = m;
+    pa.w = w;
+    pa.row_base = j0;
+    pa.ipiv = ipiv + j0;
+    pa.ipiv_rel = nullptr;
+    pa.info = info;
+    pa.info_col_base = j0;
+    pa.moves = moves;
+    pa.sync = s->sync + 2 * s->sync_slot;   // [counter, error]
+    pa.sync_next = s->sync + 2 * (1 - s->sync_slot);
+    s->sync_slot = 1 - s->sync_slot;
+    CandPtrs<T> c = cand_ptrs<T>(s);
+    pa.cand_val = c.val; pa.cand_idx = c.idx; pa.cand_rows = c.rows; pa.diag_rows = c.diag;
+    pa.spin_limit = s->spin_limit;
+    int wgs = panel_wgs_for(*s, m, wgs_req);
+    if (wgs < 0) return LU_ERR_UNSUPPORTED;
+    return launch_panel<T>(pa, wgs, st) == 0 ? 0 : LU_ERR_HIP;
+}
+
+template <typename T, typename H>
+int execute(DeviceState* s, int n, T* A, long long lda, int* ipiv, int* info, const lu_schedule_t& sch,
+            hipStream_t stream, bool mixed) {
+    const int b = sch.b;
+    const std::vector<PlanTask>* plan = get_plan(s, n, b, sch.depth);
+    if (!plan) return LU_ERR_UNSUPPORTED;
+    const int N = (n + b - 1) / b;
+    int rc;
+    if ((rc = ensure(s->moves, (size_t)N * kMovesLen * sizeof(int)))) return rc;
+    int* moves = reinterpret_cast<int*>(s->moves.ptr);
+    // mixed precision operand copies
+    H* Lh = nullptr; H* Uh = nullptr; float* rs = nullptr; float* cs = nullptr;
+    long long ldh = 0, lduh = 0;
+    if (mixed) {
+        ldh = ((long long)n + 7) / 8 * 8 + 8;
+        lduh = ((long long)n + 7) / 8 * 8 + 8;
+        if ((rc = ensure(s->lh, (size_t)n * ldh * sizeof(H)))) return rc;
+        if ((rc = ensure(s->uh, (size_t)n * lduh * sizeof(H)))) return rc;
+        if ((rc = ensure(s->rs, (size_t)N * n * sizeof(float)))) return rc;
+        if ((rc = ensure(s->cs, (size_t)N * n * sizeof(float)))) return rc;
+        Lh = reinterpret_cast<H*>(s->lh.ptr);
+        Uh = reinterpret_cast<H*>(s->uh.ptr);
+        rs = reinterpret_cast<float*>(s->rs.ptr);
+        cs = reinterpret_cast<float*>(s->cs.ptr);
+    }
+    hipStream_t streams[2] = {stream, s->panel_stream};
+    // entry join: the panel stream starts after everything already on `stream`
+    hipEvent_t ev0 = s->events[s->ev_next]; s->ev_next = (s->ev_next + 1) % kEventRing;
+    LU_HIP(hipEventRecord(ev0, stream));
+    LU_HIP(hipStreamWaitEvent(s->panel_stream, ev0, 0));
+    std::vector<int> ev_of(plan->size(), -1);
+    for (size_t ti = 0; ti < plan->size(); ++ti) {
+        const PlanTask& t = (*plan)[ti];
+        hipStream_t st = streams[t.stream];
+        for (int wv = 0; wv < t.nwait; ++wv) {
+            const int e = ev_of[t.wait[wv]];
+            if (e < 0) return LU_ERR_UNSUPPORTED;
+            LU_HIP(hipStreamWaitEvent(st, s->events[e], 0));
+        }
+        const int k = t.step;
+        const int kb = k * b;
+        const int wk = std::min(b, n - kb);
+        int* mv = moves + (size_t)k * kMovesLen;
+        if (t.kind == kTaskPanel) {
+            if ((rc = run_panel<T>(s, A, lda, n, kb, wk, ipiv, info, mv, sch.panel_cus, st))) return rc;
+            if (mixed && n - kb - wk > 0) {
+                if (launch_l21_half<H>(reinterpret_cast<const float*>(A) + (kb + wk) + (long long)kb * lda, lda,
+                                       n - kb - wk, wk, Lh + (long long)(kb + wk) * ldh + kb, ldh,
+                                       rs + (size_t)k * n + (kb + wk), st))
+                    return LU_ERR_HIP;
+            }
+        } else if (t.kind == kTaskUpdate) {
+            SwapTrsmArgs<T, H> sa;
+            sa.A = A; sa.lda = lda; sa.r0 = kb; sa.w = wk; sa.moves = mv;
+            sa.c0 = t.col_begin; sa.c1 = t.col_end; sa.bn = 0;
+            sa.uh = mixed ? Uh + kb : nullptr;
+            sa.lduh = lduh;
+            sa.cs = mixed ? cs + (size_t)k * n : nullptr;
+            if (launch_swap_trsm<T, H>(sa, st)) return LU_ERR_HIP;
+            const int M = n - kb - wk, Nc = t.col_end - t.col_begin;
+            if (M > 0) {
+                if (mixed) {
+                    if (launch_gemm_half<H>(M, Nc, wk, Lh + (long long)(kb + wk) * ldh + kb, (int)ldh,
+                                            Uh + (long long)t.col_begin * lduh + kb, (int)lduh,
+                                            rs + (size_t)k * n + (kb + wk), cs + (size_t)k * n + t.col_begin,
+                                            reinterpret_cast<float*>(A) + (kb + wk) + (long long)t.col_begin * lda,
+                                            (int)lda, st))
+                        return LU_ERR_HIP;
+                } else {
+                    hipEvent_t stop;
+                    if ((rc = timed_begin(st, M, Nc, wk, &stop))) return rc;
+                    if (launch_gemm<T>(M, Nc, wk, A + (kb + wk) + (long long)kb * lda, (int)lda,
+                                       A + kb + (long long)t.col_begin * lda, (int)lda,
+                                       A + (kb + wk) + (long long)t.col_begin * lda, (int)lda, st))
+                        return LU_ERR_HIP;
+                    if (stop) LU_HIP(hipEventRecord(stop, st));
+                }
+            }
+        } else {
+            if (launch_lswap<T>(A, lda, kb, mv, t.col_begin, t.col_end, st)) return LU_ERR_HIP;
+        }
+        if (t.record) {
+            const int e = s->ev_next;
+            s->ev_next = (s->ev_next + 1) % kEventRing;
+            LU_HIP(hipEventRecord(s->events[e], st));
+            ev_of[ti] = e;
+        }
+    }
+    // exit join
+    hipEvent_t ev1 = s->events[s->ev_next]; s->ev_next = (s->ev_next + 1) % kEventRing;
+    LU_HIP(hipEventRecord(ev1, s->panel_stream));
+    LU_HIP(hipStreamWaitEvent(stream, ev1, 0));
+    return 0;
+}
+
+int check_sched(const lu_schedule_t* s) {
+    if (!s) return 0;
+    if (s->b > 0 && !valid_b(s->b)) return -6;
+    if (s->depth > 2) return -6;
+    if (s->panel_cus > 256) return -6;
+    return 0;
+}
+
+}  // namespace
+
+int factor_impl(int n, void* A, int lda, lu_precision_t prec, int* ipiv, const lu_schedule_t* sched, int* d_info,
+                hipStream_t stream) {
+    if (n < 0) return -1;
+    if (!A && n > 0) return -2;
+    if (lda < std::max(1, n)) return -3;
+    if (!ipiv && n > 0) return -4;
+    if (prec < LU_FP64 || prec > LU_MIXED_BF16) return -5;
+    if (int r = check_sched(sched)) return r;
+    if (n == 0) return 0;
+    int err;
+    DeviceState* s = device_state(&err);
+    if (!s) return err;
+    lu_schedule_t sch;
+    resolve_schedule(n, prec, sched, &sch);
+    if (sch.b > n) sch.b = std::max(32, std::min(sch.b, ((n + 31) / 32) * 32));
+    int* info = d_info ? d_info : s->info;
+    if (!d_info && launch_fill_zero(s->info, sizeof(int), stream)) return LU_ERR_HIP;
+    s->last_stream = stream;
+    s->last_info = info;
+    switch (prec) {
+    case LU_FP64:
+        return execute<double, _Float16>(s, n, reinterpret_cast<double*>(A), lda, ipiv, info, sch, stream, false);
+    case LU_FP32:
+        return execute<float, _Float16>(s, n, reinterpret_cast<float*>(A), lda, ipiv, info, sch, stream, false);
+    case LU_MIXED_FP16:
+        return execute<float, _Float16>(s, n, reinterpret_cast<float*>(A), lda, ipiv, info, sch, stream, true);
+    case LU_MIXED_BF16:
+        return execute<float, __bf16>(s, n, reinterpret_cast<float*>(A), lda, ipiv, info, sch, stream, true);
+    }
+    return -5;
+}
+
+int schedule_for(int n, lu_precision_t prec, lu_schedule_t* out) {
+    resolve_schedule(n, prec, nullptr, out);
+    return 0;
+}
+
+}  // namespace lu
+
+// ======================================================================= C ABI
+extern "C" {
+
+int lu_factor(int n, double* A, int lda, int* ipiv, hipStream_t stream) {
+    return lu::factor_impl(n, A, lda, LU_FP64, ipiv, nullptr, nullptr, stream);
+}
+
+int lu_factor_ex(int n, void* A, int lda, lu_precision_t prec, int* ipiv, const lu_schedule_t* sched, int* d_info,
+                 hipStream_t stream) {
+    return lu::factor_impl(n, A, lda, prec, ipiv, sched, d_info, stream);
+}
+
+int lu_factor_info(int* info) {
+    if (!info) return -1;
+    int err;
+    lu::DeviceState* s = lu::device_state(&err);
+    if (!s) return err;
+    LU_HIP(hipStreamSynchronize(s->last_stream));
+    LU_HIP(hipStreamSynchronize(s->panel_stream));
+    int h = 0;
+    unsigned e[4] = {0, 0, 0, 0};
+    LU_HIP(hipMemcpy(&h, s->last_info ? s->last_info : s->info, sizeof(int), hipMemcpyDeviceToHost));
+    LU_HIP(hipMemcpy(e, s->sync, 4 * sizeof(unsigned), hipMemcpyDeviceToHost));
+    *info = h;
+    if (e[1] || e[3]) {
+        // a barrier timed out: reset the words so later factorizations start clean
+        LU_HIP(hipMemset(s->sync, 0, 8 * sizeof(unsigned)));
+        return LU_ERR_BARRIER;
+    }
+    return 0;
+}
+
+int lu_schedule_default(int n, lu_precision_t prec, lu_schedule_t* out) {
+    if (!out) return -3;
+    return lu::schedule_for(n, prec, out);
+}
+
+void lu_release(void) { lu::release_all(); }
+
+// ---- per-kernel entry points ------------------------------------------------
+int lu_k_panel(lu_precision_t prec, int m, int w, void* P, int ldp, int* ipiv_rel, int wgs, int* d_info,
+               hipStream_t stream) {
+    if (prec < LU_FP64 || prec > LU_MIXED_BF16) return -1;
+    if (m < 1) return -2;
+    if (w < 1 || w > m || w > 512) return -3;
+    if (!P) return -4;
+    if (ldp < m) return -5;
+    if (!ipiv_rel) return -6;
+    int err;
+    lu::DeviceState* s = lu::device_state(&err);
+    if (!s) return err;
+    int rc = lu::ensure(s->moves, (size_t)lu::kMovesLen * sizeof(int));
+    if (rc) return rc;
+    lu::PanelArgs<double> pd;
+    (void)pd;
+    // the panel kernel writes matrix-row pivots; with row_base 0 they are panel-relative
+    if (prec == LU_FP64)
+        return lu::run_panel<double>(s, reinterpret_cast<double*>(P), ldp, m, 0, w, ipiv_rel, d_info,
+                                     reinterpret_cast<int*>(s->moves.ptr), wgs, stream);
+    return lu::run_panel<float>(s, reinterpret_cast<float*>(P), ldp, m, 0, w, ipiv_rel, d_info,
+                                reinterpret_cast<int*>(s->moves.ptr), wgs, stream);
+}
+
+int lu_k_update(lu_precision_t prec, int m, int w, int ncols, const void* L, int ldl, const int* ipiv_rel, void* C,
+                int ldc, hipStream_t stream) {
+    if (prec < LU_FP64 || prec > LU_MIXED_BF16) return -1;
+    if (m < 1) return -2;
+    if (w < 1 || w > m || w > 512) return -3;
+    if (ncols < 0) return -4;
+    if (!L) return -5;
+    if (ldl < m) return -6;
+    if (!ipiv_rel) return -7;
+    if (!C && ncols > 0) return -8;
+    if (ldc < m) return -9;
+    if (ncols == 0) return 0;
+    int err;
+    lu::DeviceState* s = lu::device_state(&err);
+    if (!s) return err;
+    int rc = lu::ensure(s->solve_moves, (size_t)lu::kMovesLen * sizeof(int));
+    if (rc) return rc;
+    int* mv = reinterpret_cast<int*>(s->solve_moves.ptr);
+    if (lu::launch_moves(ipiv_rel, w, m, mv, stream)) return LU_ERR_HIP;
+    // The kernels address the panel and the block through one matrix view:
+    // they need L and C to share the leading dimension.
+    if (ldl != ldc) return LU_ERR_UNSUPPORTED;
+    // Treat [L | C] as columns of one matrix starting at column 0 = L: the update
+    // kernels take A (matrix base), r0 = 0 and column ranges; C = L + off*ldc.
+    const long long off_bytes = reinterpret_cast<const char*>(C) - reinterpret_cast<const char*>(L);
+    const size_t esz = prec == LU_FP64 ? 8 : 4;
+    if (off_bytes <= 0 || off_bytes % (esz * (long long)ldc) != 0) return LU_ERR_UNSUPPORTED;
+    const int c0 = (int)(off_bytes / (esz * (long long)ldc));
+    if (c0 < w) return LU_ERR_UNSUPPORTED;
+    if (prec == LU_FP64) {
+        double* A = const_cast<double*>(reinterpret_cast<const double*>(L));
+        lu::SwapTrsmArgs<double, _Float16> sa{A, ldl, 0, w, mv, c0, c0 + ncols, 0, nullptr, 0, nullptr};
+        if (lu::launch_swap_trsm<double, _Float16>(sa, stream)) return LU_ERR_HIP;
+        if (m > w && lu::launch_gemm<double>(m - w, ncols, w, A + w, ldl, A + (long long)c0 * ldl, ldl,
+                                             A + w + (long long)c0 * ldl, ldl, stream))
+            return LU_ERR_HIP;
+    } else {
+        float* A = const_cast<float*>(reinterpret_cast<const float*>(L));
+        lu::SwapTrsmArgs<float, _Float16> sa{A, ldl, 0, w, mv, c0, c0 + ncols, 0, nullptr, 0, nullptr};
+        if (lu::launch_swap_trsm<float, _Float16>(sa, stream)) return LU_ERR_HIP;
+        if (m > w && lu::launch_gemm<float>(m - w, ncols, w, A + w, ldl, A + (long long)c0 * ldl, ldl,
+                                            A + w + (long long)c0 * ldl, ldl, stream))
+            return LU_ERR_HIP;
+    }
+    return 0;
+}
+
+int lu_k_gemm(lu_precision_t prec, int m, int n, int k, const void* A, int lda, const void* B, int ldb, void* C,
+              int ldc, hipStream_t stream) {
+    if (prec < LU_FP64 || prec > LU_MIXED_BF16) return -1;
+    if (m < 0) return -2;
+    if (n < 0) return -3;
+    if (k < 0) return -4;
+    if (!A && m * k > 0) return -5;
+    if (lda < std::max(1, m)) return -6;
+    if (!B && k * n > 0) return -7;
+    if (ldb < std::max(1, k)) return -8;
+    if (!C && m * n > 0) return -9;
+    if (ldc < std::max(1, m)) return -10;
+    if (m == 0 || n == 0 || k == 0) return 0;
+    if (prec == LU_FP64)
+        return lu::launch_gemm<double>(m, n, k, (const double*)A, lda, (const double*)B, ldb, (double*)C, ldc,
+                                       stream) ? LU_ERR_HIP : 0;
+    if (prec == LU_FP32)
+        return lu::launch_gemm<float>(m, n, k, (const float*)A, lda, (const float*)B, ldb, (float*)C, ldc,
+                                      stream) ? LU_ERR_HIP : 0;
+    // mixed: round the operands to half precision with power-of-two scales first
+    int err;
+    lu::DeviceState* s = lu::device_state(&err);
+    if (!s) return err;
+    const long long ldh = ((long long)k + 7) / 8 * 8 + 8;
+    int rc;
+    const size_t hsz = 2;
+    if ((rc = lu::ensure(s->lh, (size_t)m * ldh * hsz))) return rc;
+    if ((rc = lu::ensure(s->uh, (size_t)n * ldh * hsz))) return rc;
+    if ((rc = lu::ensure(s->rs, (size_t)m * sizeof(float)))) return rc;
+    if ((rc = lu::ensure(s->cs, (size_t)n * sizeof(float)))) return rc;
+    float* rs = (float*)s->rs.ptr;
+    float* cs = (float*)s->cs.ptr;
+    // A rows -> Lh (row-major, one scale per row); B columns -> Uh (k contiguous, one scale per column)
+    if (prec == LU_MIXED_FP16) {
+        if (lu::launch_l21_half<_Float16>((const float*)A, lda, m, k, (_Float16*)s->lh.ptr, ldh, rs, stream))
+            return LU_ERR_HIP;
+        if (lu::launch_cols_half<_Float16>((const float*)B, ldb, k, n, (_Float16*)s->uh.ptr, ldh, cs, stream))
+            return LU_ERR_HIP;
+        return lu::launch_gemm_half<_Float16>(m, n, k, (_Float16*)s->lh.ptr, (int)ldh, (_Float16*)s->uh.ptr,
+                                              (int)ldh, rs, cs, (float*)C, ldc, stream) ? LU_ERR_HIP : 0;
+    }
+    if (lu::launch_l21_half<__bf16>((const float*)A, lda, m, k, (__bf16*)s->lh.ptr, ldh, rs, stream))
+        return LU_ERR_HIP;
+    if (lu::launch_cols_half<__bf16>((const float*)B, ldb, k, n, (__bf16*)s->uh.ptr, ldh, cs, stream))
+        return LU_ERR_HIP;
+    return lu::launch_gemm_half<__bf16>(m, n, k, (__bf16*)s->lh.ptr, (int)ldh, (__bf16*)s->uh.ptr, (int)ldh, rs,
+                                        cs, (float*)C, ldc, stream) ? LU_ERR_HIP : 0;
+}
+
+int lu_k_laswp(lu_precision_t prec, int m, int w, int ncols, const int* ipiv_rel, void* C, int ldc,
+               hipStream_t stream) {
+    if (prec < LU_FP64 || prec > LU_MIXED_BF16) return -1;
+    if (m < 1) return -2;
+    if (w < 1 || w > m || w > 512) return -3;
+    if (ncols < 0) return -4;
+    if (!ipiv_rel) return -5;
+    if (!C && ncols > 0) return -6;
+    if (ldc < m) return -7;
+    if (ncols == 0) return 0;
+    int err;
+    lu::DeviceState* s = lu::device_state(&err);
+    if (!s) return err;
+    int rc = lu::ensure(s->solve_moves, (size_t)lu::kMovesLen * sizeof(int));
+    if (rc) return rc;
+    int* mv = reinterpret_cast<int*>(s->solve_moves.ptr);
+    if (lu::launch_moves(ipiv_rel, w, m, mv, stream)) return LU_ERR_HIP;
+    if (prec == LU_FP64) return lu::launch_lswap<double>((double*)C, ldc, 0, mv, 0, ncols, stream) ? LU_ERR_HIP : 0;
+    return lu::launch_lswap<float>((float*)C, ldc, 0, mv, 0, ncols, stream) ? LU_ERR_HIP : 0;
+}
+
+int lu_k_timing(int enable) {
+    if (enable != 0 && enable != 1) return -1;
+    lu::g_timing.on = enable == 1;
+    if (enable) lu::g_timing.used = 0;
+    return 0;
+}
+
+int lu_k_timing_read(double* ms, double* flops, int* launches) {
+    if (!ms) return -1;
+    if (!flops) return -2;
+    if (!launches) return -3;
+    double t = 0, f = 0;
+    for (size_t i = 0; i < lu::g_timing.used; ++i) {
+        float e = 0.f;
+        LU_HIP(hipEventSynchronize(lu::g_timing.ev[2 * i + 1]));
+        LU_HIP(hipEventElapsedTime(&e, lu::g_timing.ev[2 * i], lu::g_timing.ev[2 * i + 1]));
+        t += e;
+        f += lu::g_timing.flops[i];
+    }
+    *ms = t;
+    *flops = f;
+    *launches = (int)lu::g_timing.used;
+    return 0;
+}
+
+int lu_k_probe_mfma_f64(double* out, hipStream_t stream) {
+    if (!out) return -1;
+    return lu::launch_probe_mfma_f64(out, stream) ? LU_ERR_HIP : 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,154 @@
+// Device helpers shared by the gfx950 kernels of the LU library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.hpp"
+
+namespace lu {
+
+constexpr int kWave = 64;
+
+template <typename T> __device__ __forceinline__ T dabs(T x) { return x < T(0) ? -x : x; }
+template <> __device__ __forceinline__ double dabs<double>(double x) { return fabs(x); }
+template <> __device__ __forceinline__ float dabs<float>(float x) { return fabsf(x); }
+
+// (value, index) arg-max with the smallest index winning ties; NaN never wins.
+template <typename T>
+__device__ __forceinline__ void argmax_merge(T& v, int& i, T ov, int oi) {
+    if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
+}
+
+template <typename T>
+__device__ __forceinline__ void wave_argmax(T& v, int& i) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        T ov = __shfl_xor(v, off, kWave);
+        int oi = __shfl_xor(i, off, kWave);
+        argmax_merge(v, i, ov, oi);
+    }
+}
+
+// Device-wide barrier among the gridDim.x work-groups of one launch.  All of
+// them must be resident at once (the host sizes the grid for that).  The
+// counter starts at 0 for the launch; barrier number `epoch` (1-based) waits
+// until the counter reaches epoch*gridDim.x.  The wait is bounded: past
+// `limit` ticks of the constant-rate wall clock, or when another work-group
+// has already failed, the error word is set and true is returned so that the
+// caller exits instead of hanging.
+__device__ __forceinline__ bool grid_barrier(unsigned* counter, unsigned* err, unsigned epoch,
+                                             long long limit) {
+    __shared__ int s_fail;
+    // every wave makes its own global writes visible device-wide before the
+    // work-group arrives, and re-reads device-wide data after it leaves
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned target = epoch * gridDim.x;
+        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        int fail = 0;
+        const long long t0 = wall_clock64();
+        while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) { fail = 1; break; }
+            if (wall_clock64() - t0 > limit) {
+                __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                fail = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        s_fail = fail;
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return s_fail != 0;
+}
+
+// Composition of a run of row interchanges into one gather/scatter.
+//
+// Steps t = 0..w-1 interchange rows t and p[t] (p[t] >= t, rows relative to
+// the first row of the run).  Rows 0..w-1 are the "top" rows; rows >= w that
+// some p[t] names are "extra" rows.  With
+//   L(t)    = the latest step t' != t with p[t'] == t      (none: -1)
+//   f(t)    = f(L(t)) if L(t) >= 0 else t   (the row whose data sits in top
+//             row t when step t begins)
+//   prev(t) = the latest step t' < t with p[t'] == p[t]    (none: -1)
+// the result of all w interchanges is
+//   top row t   <- f(t)                     if p[t] == t
+//               <- f(prev(t)) or p[t]       otherwise (prev(t) >= 0 / < 0)
+//   extra row e <- f(t) for the last step t with p[t] == e.
+// One work-group computes this in LDS: L by atomic max, f by pointer
+// jumping, prev by a bitonic sort of (p[t], t).  w <= kMovesMaxW.
+//
+// Output layout (int[kMovesLen]), rows relative to the run, only rows whose
+// content changes:
+//   [0] number of top moves, [1] number of extra moves,
+//   [2 + 2s], [3 + 2s]                      (dst, src) of top move s
+//   [kMovesExtra + 2e], [kMovesExtra+1+2e]  (dst, src) of extra move e
+
+struct MovesScratch {
+    int key[kMovesMaxW];       // sorted (p << 10 | t)
+    int last_top[kMovesMaxW];
+    int ptr_a[kMovesMaxW];
+    int ptr_b[kMovesMaxW];
+    int count_top, count_extra;
+};
+
+__device__ inline void compose_moves(const int* p, int w, int* moves, MovesScratch& s) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int t = tid; t < kMovesMaxW; t += nt) {
+        s.last_top[t] = -1;
+        s.key[t] = t < w ? ((p[t] << 10) | t) : 0x7fffffff;
+    }
+    if (tid == 0) { s.count_top = 0; s.count_extra = 0; }
+    __syncthreads();
+    for (int t = tid; t < w; t += nt) {
+        int q = p[t];
+        if (q < w && q != t) atomicMax(&s.last_top[q], t);
+    }
+    // bitonic sort of key[0..kMovesMaxW)
+    for (int size = 2; size <= kMovesMaxW; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __syncthreads();
+            for (int i = tid; i < kMovesMaxW / 2; i += nt) {
+                int lo = 2 * i - (i & (stride - 1));
+                int hi = lo + stride;
+                bool up = ((lo & size) == 0);
+                int a = s.key[lo], b = s.key[hi];
+                if ((a > b) == up) { s.key[lo] = b; s.key[hi] = a; }
+            }
+        }
+    }
+    __syncthreads();
+    for (int t = tid; t < w; t += nt) s.ptr_a[t] = s.last_top[t] >= 0 ? s.last_top[t] : t;
+    __syncthreads();
+    int* cur = s.ptr_a;
+    int* nxt = s.ptr_b;
+    for (int round = 0; (1 << round) < w; ++round) {
+        for (int t = tid; t < w; t += nt) nxt[t] = cur[cur[t]];
+        __syncthreads();
+        int* tmp = cur; cur = nxt; nxt = tmp;
+    }
+    // cur[t] = f(t).  prev from the sorted keys: key index i holds (p, t).
+    for (int i = tid; i < w; i += nt) {
+        const int k = s.key[i];
+        const int t = k & 1023, q = k >> 10;
+        const int prv = (i > 0 && (s.key[i - 1] >> 10) == q) ? (s.key[i - 1] & 1023) : -1;
+        const bool last = (i + 1 >= w) || ((s.key[i + 1] >> 10) != q);
+        const int src = (q == t) ? cur[t] : (prv >= 0 ? cur[prv] : q);
+        if (src != t) {
+            const int slot = atomicAdd(&s.count_top, 1);
+            moves[2 + 2 * slot] = t;
+            moves[3 + 2 * slot] = src;
+        }
+        if (q >= w && last) {
+            const int slot = atomicAdd(&s.count_extra, 1);
+            moves[kMovesExtra + 2 * slot] = q;
+            moves[kMovesExtra + 1 + 2 * slot] = cur[t];
+        }
+    }
+    __syncthreads();
+    if (tid == 0) { moves[0] = s.count_top; moves[1] = s.count_extra; }
+}
+
+}  // namespace lu

@@ -1,0 +1,323 @@
+// Trailing-matrix update, RL3 of LU_blk (paper Sec. 3.5): C -= A * B with
+// A = A21 (m x k), B = A12 (k x n) and k = the block size b.  This is where
+// the flops are (Sec. 3.2: the panel width is kept small so that most work
+// is this compute-bound update).
+//
+// gfx950 MFMA tiles, 256 threads = 4 waves per work-group, 128 x 128 output
+// tile per work-group (64 x 64 per wave = 4 x 4 MFMA 16x16 blocks).  The
+// operands are staged through LDS, double-buffered, one k-tile ahead.
+//
+// Operand roles are swapped inside the MFMA: the instruction's first operand
+// takes B (so its 16 output rows run along C's columns) and its second takes
+// -A (output columns along C's rows).  A lane then holds 16 consecutive ROWS
+// of one C column, which is what column-major C wants for coalesced loads
+// and stores.  For FP64/FP32 the accumulators start from C itself, so the
+// update is C + sum_k (-a_ik) b_kj accumulated in the matrix core.
+//
+// Element (i,j) of C sees the same sequence of operations whatever the tile
+// it falls in, so splitting the update into several launches (the look-ahead
+// schedule does) leaves the result bit-identical.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace lu {
+
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr int kBM = 128, kBN = 128, kThreads = 256;
+
+template <typename T> struct Acc;
+template <> struct Acc<double> { typedef v4d type; };
+template <> struct Acc<float> { typedef v4f type; };
+
+__device__ __forceinline__ v4d mfma(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mfma(float a, float b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Map the linear work-group id to a (tile_m, tile_n) pair.  Work-groups are
+// dealt to the 8 XCDs round-robin; this remap gives each XCD a contiguous
+// band of tile columns so that its L2 keeps reusing the same B columns.
+__device__ __forceinline__ void tile_of(int tiles_m, int tiles_n, int& tm, int& tn) {
+    const int nt = tiles_m * tiles_n;
+    int bid = blockIdx.x;
+    const int per = nt / 8;
+    if (per > 0 && bid < per * 8) bid = (bid % 8) * per + bid / 8;
+    tm = bid % tiles_m;
+    tn = bid / tiles_m;
+}
+
+template <typename T, int BK>
+__global__ __launch_bounds__(kThreads, 2) void gemm_nn_sub(int M, int N, int K, const T* __restrict__ A,
+                                                            int lda, const T* __restrict__ B, int ldb,
+                                                            T* __restrict__ C, int ldc) {
+    typedef typename Acc<T>::type V4;
+    constexpr int PA = 2, PB = 1;
+    __shared__ T As[2][BK][kBM + PA];
+    __shared__ T Bs[2][kBN][BK + PB];
+
+    const int tiles_m = (M + kBM - 1) / kBM, tiles_n = (N + kBN - 1) / kBN;
+    int tm, tn;
+    tile_of(tiles_m, tiles_n, tm, tn);
+    const int m0 = tm * kBM, n0 = tn * kBN;
+    const int tid = threadIdx.x;
+    const int wave = tid / 64, lane = tid % 64;
+    const int l16 = lane % 16, lg = lane / 16;
+    const int wm = wave % 2, wn = wave / 2;
+
+    // accumulators start from C
+    V4 acc[4][4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+        const int row = m0 + wm * 64 + rb * 16 + l16;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int col = n0 + wn * 64 + cb * 16 + 4 * lg + r;
+                acc[rb][cb][r] = (row < M && col < N) ? C[row + (long long)col * ldc] : T(0);
+            }
+        }
+    }
+
+    // global -> register staging
+    constexpr int AL = BK * kBM / kThreads;   // A elements per thread
+    constexpr int BL = BK * kBN / kThreads;   // B elements per thread
+    T ra[AL], rbv[BL];
+    const int a_row = tid % kBM, a_k0 = tid / kBM;              // A: rows contiguous
+    constexpr int AKS = kThreads / kBM;
+    const int b_col = tid / (kThreads / kBN), b_kh = tid % (kThreads / kBN);   // B: k contiguous
+    constexpr int BKS = BK / (kThreads / kBN);
+
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int r = 0; r < AL; ++r) {
+            const int kk = a_k0 + AKS * r;
+            const int gr = m0 + a_row, gk = k0 + kk;
+            ra[r] = (gr < M && gk < K) ? A[gr + (long long)gk * lda] : T(0);
+        }
+#pragma unroll
+        for (int e = 0; e < BL; ++e) {
+            const int kk = b_kh * BKS + e;
+            const int gc = n0 + b_col, gk = k0 + kk;
+            rbv[e] = (gc < N && gk < K) ? B[gk + (long long)gc * ldb] : T(0);
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < AL; ++r) As[buf][a_k0 + AKS * r][a_row] = -ra[r];
+#pragma unroll
+        for (int e = 0; e < BL; ++e) Bs[buf][b_col][b_kh * BKS + e] = rbv[e];
+    };
+
+    const int nk = (K + BK - 1) / BK;
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) load((kt + 1) * BK);
+#pragma unroll
+        for (int ks = 0; ks < BK / 4; ++ks) {
+            T af[4], bf[4];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) af[rb] = As[cur][ks * 4 + lg][wm * 64 + rb * 16 + l16];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) bf[cb] = Bs[cur][wn * 64 + cb * 16 + l16][ks * 4 + lg];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = mfma(bf[cb], af[rb], acc[rb][cb]);
+        }
+        if (kt + 1 < nk) store(cur ^ 1);
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+        const int row = m0 + wm * 64 + rb * 16 + l16;
+        if (row < M) {
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int col = n0 + wn * 64 + cb * 16 + 4 * lg + r;
+                    if (col < N) C[row + (long long)col * ldc] = acc[rb][cb][r];
+                }
+            }
+        }
+    }
+}
+
+// Mixed precision: C (FP32) -= diag(rs) (Ah Bh) diag(cs), Ah = FP16/BF16 rows
+// of A21 stored k-contiguous (row-major, leading dimension lda_h), Bh = the
+// U12 columns stored k-contiguous (column-major, ldb_h); rs / cs are the
+// exact powers of two that undo the operand scaling.  FP32 accumulation in
+// v_mfma_f32_16x16x32_{f16,bf16}.
+template <typename H> struct HalfOps;
+template <> struct HalfOps<_Float16> {
+    typedef v8h vec;
+    static __device__ __forceinline__ v4f mma(vec a, vec b, v4f c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct HalfOps<__bf16> {
+    typedef v8bf vec;
+    static __device__ __forceinline__ v4f mma(vec a, vec b, v4f c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+
+template <typename H>
+__global__ __launch_bounds__(kThreads, 2) void gemm_half_sub(int M, int N, int K, const H* __restrict__ Ah,
+                                                              int lda_h, const H* __restrict__ Bh, int ldb_h,
+                                                              const float* __restrict__ rs,
+                                                              const float* __restrict__ cs,
+                                                              float* __restrict__ C, int ldc) {
+    typedef typename HalfOps<H>::vec VH;
+    constexpr int BK = 64;              // two MFMA k-steps of 32
+    constexpr int PADH = 8;             // halves of padding per LDS row
+    __shared__ H As[2][kBM][BK + PADH];
+    __shared__ H Bs[2][kBN][BK + PADH];
+
+    const int tiles_m = (M + kBM - 1) / kBM, tiles_n = (N + kBN - 1) / kBN;
+    int tm, tn;
+    tile_of(tiles_m, tiles_n, tm, tn);
+    const int m0 = tm * kBM, n0 = tn * kBN;
+    const int tid = threadIdx.x;
+    const int wave = tid / 64, lane = tid % 64;
+    const int l16 = lane % 16, lg = lane / 16;
+    const int wm = wave % 2, wn = wave / 2;
+
+    v4f acc[4][4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    // each thread moves 4 chunks of 8 halves (16 B) for A and for B per k-tile
+    const int ld_row = tid / 8 * 1, ld_chunk = tid % 8;      // 32 rows x 8 chunks per pass
+    VH ra[4], rb4[4];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int row = ld_row + 32 * p;
+            const int gk = k0 + ld_chunk * 8;
+            const int gr = m0 + row, gc = n0 + row;
+            VH za;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) za[e] = H(0.f);
+            ra[p] = za;
+            rb4[p] = za;
+            if (gr < M) {
+                if (gk + 8 <= K) ra[p] = *reinterpret_cast<const VH*>(Ah + (long long)gr * lda_h + gk);
+                else for (int e = 0; e < 8; ++e) if (gk + e < K) ra[p][e] = Ah[(long long)gr * lda_h + gk + e];
+            }
+            if (gc < N) {
+                if (gk + 8 <= K) rb4[p] = *reinterpret_cast<const VH*>(Bh + (long long)gc * ldb_h + gk);
+                else for (int e = 0; e < 8; ++e) if (gk + e < K) rb4[p][e] = Bh[(long long)gc * ldb_h + gk + e];
+            }
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            *reinterpret_cast<VH*>(&As[buf][ld_row + 32 * p][ld_chunk * 8]) = ra[p];
+            *reinterpret_cast<VH*>(&Bs[buf][ld_row + 32 * p][ld_chunk * 8]) = rb4[p];
+        }
+    };
+    const int nk = (K + BK - 1) / BK;
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) load((kt + 1) * BK);
+#pragma unroll
+        for (int ks = 0; ks < BK / 32; ++ks) {
+            VH af[4], bf[4];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+                af[rb] = *reinterpret_cast<const VH*>(&As[cur][wm * 64 + rb * 16 + l16][ks * 32 + lg * 8]);
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+                bf[cb] = *reinterpret_cast<const VH*>(&Bs[cur][wn * 64 + cb * 16 + l16][ks * 32 + lg * 8]);
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = HalfOps<H>::mma(bf[cb], af[rb], acc[rb][cb]);
+        }
+        if (kt + 1 < nk) store(cur ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+        const int row = m0 + wm * 64 + rb * 16 + l16;
+        if (row < M) {
+            const float rsc = rs[row];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int col = n0 + wn * 64 + cb * 16 + 4 * lg + r;
+                    if (col < N) {
+                        float* p = C + row + (long long)col * ldc;
+                        *p = *p - (acc[rb][cb][r] * rsc) * cs[col];
+                    }
+                }
+            }
+        }
+    }
+}
+
+}  // namespace
+
+template <typename T>
+int launch_gemm(int M, int N, int K, const T* A, int lda, const T* B, int ldb, T* C, int ldc,
+                hipStream_t stream) {
+    if (M <= 0 || N <= 0 || K <= 0) return 0;
+    const int tiles = ((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
+    hipLaunchKernelGGL((gemm_nn_sub<T, 16>), dim3(tiles), dim3(kThreads), 0, stream, M, N, K, A, lda, B,
+                       ldb, C, ldc);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <typename H>
+int launch_gemm_half(int M, int N, int K, const H* Ah, int lda_h, const H* Bh, int ldb_h,
+                     const float* rs, const float* cs, float* C, int ldc, hipStream_t stream) {
+    if (M <= 0 || N <= 0 || K <= 0) return 0;
+    const int tiles = ((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
+    hipLaunchKernelGGL((gemm_half_sub<H>), dim3(tiles), dim3(kThreads), 0, stream, M, N, K, Ah, lda_h, Bh,
+                       ldb_h, rs, cs, C, ldc);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template int launch_gemm<double>(int, int, int, const double*, int, const double*, int, double*, int,
+                                 hipStream_t);
+template int launch_gemm<float>(int, int, int, const float*, int, const float*, int, float*, int, hipStream_t);
+template int launch_gemm_half<_Float16>(int, int, int, const _Float16*, int, const _Float16*, int,
+                                        const float*, const float*, float*, int, hipStream_t);
+template int launch_gemm_half<__bf16>(int, int, int, const __bf16*, int, const __bf16*, int, const float*,
+                                      const float*, float*, int, hipStream_t);
+
+// One MFMA on lane-indexed values, to check the operand/result lane layout.
+__global__ void probe_mfma_f64_kernel(double* out) {
+    const int l = threadIdx.x;
+    v4d c = {0, 0, 0, 0};
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64((double)l, 100.0 + l, c, 0, 0, 0);
+    for (int r = 0; r < 4; ++r) out[l * 4 + r] = c[r];
+}
+
+int launch_probe_mfma_f64(double* out, hipStream_t stream) {
+    hipLaunchKernelGGL(probe_mfma_f64_kernel, dim3(1), dim3(64), 0, stream, out);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace lu

@@ -1,0 +1,105 @@
+// Host-side launchers of the gfx950 kernels (one translation unit per kernel
+// family).  All pointers are device pointers; all launches are asynchronous.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace lu {
+
+// Composed row interchanges of one panel (see compose_moves in common.hpp):
+// [0] top moves, [1] extra moves, top (dst, src) pairs from [2], extra pairs
+// from [kMovesExtra]; rows relative to the panel's first row.
+constexpr int kMovesMaxW = 512;
+constexpr int kMovesExtra = 2 + 2 * kMovesMaxW;
+constexpr int kMovesLen = 2 + 4 * kMovesMaxW;
+
+template <typename T>
+struct PanelArgs {
+    T* A;                 // panel top-left element (panel row 0, panel column 0)
+    int lda;
+    int m, w;             // panel rows (from its top row to the last matrix row), width
+    int row_base;         // matrix row index of panel row 0
+    int* ipiv;            // ipiv[d] = row_base + pivot row, for panel columns d = 0..w-1
+    int* ipiv_rel;        // optional panel-relative pivots
+    int* info;            // optional LAPACK info word (first zero pivot, 1-based)
+    int info_col_base;    // matrix column of panel column 0
+    int* moves;           // optional composed interchanges (kMovesLen ints)
+    unsigned* sync;       // [0] barrier counter (0 at launch), [1] error word
+    unsigned* sync_next;  // counter of the alternate slot, zeroed by this launch
+    T* cand_val;          // [2][P]
+    int* cand_idx;        // [2][P]
+    T* cand_rows;         // [2][P][16]
+    T* diag_rows;         // [2][16]
+    long long spin_limit; // barrier wait bound, wall-clock ticks
+};
+
+template <typename T>
+int launch_panel(const PanelArgs<T>& args, int wgs, hipStream_t stream);
+int panel_max_rows_per_wg();
+
+template <typename T, typename H>
+struct SwapTrsmArgs {
+    T* A;                 // matrix base
+    long long lda;
+    int r0;               // first row (and column) of the panel of this step
+    int w;                // panel width
+    const int* moves;     // composed interchanges of the panel (rows relative to r0)
+    int c0, c1;           // columns to process
+    int bn;               // columns per work-group (set by the launcher)
+    H* uh;                // optional half copy of U12: uh[col*lduh + t], t = row - r0
+    long long lduh;
+    float* cs;            // per-column inverse scales of uh, indexed by column
+};
+
+template <typename T, typename H>
+int launch_swap_trsm(const SwapTrsmArgs<T, H>& args, hipStream_t stream);
+template <typename T>
+int launch_lswap(T* A, long long lda, int r0, const int* moves, int c0, int c1, hipStream_t stream);
+int launch_moves(const int* ipiv_rel, int w, int m, int* moves, hipStream_t stream);
+int launch_chunk_moves(const int* ipiv, int n, int W, int* moves, hipStream_t stream);
+template <typename H>
+int launch_l21_half(const float* A, long long lda, int m, int w, H* Lh, long long ldh, float* rs,
+                    hipStream_t stream);
+
+template <typename H>
+int launch_cols_half(const float* B, long long ldb, int k, int n, H* Uh, long long ldh, float* cs,
+                     hipStream_t stream);
+
+template <typename T>
+int launch_gemm(int M, int N, int K, const T* A, int lda, const T* B, int ldb, T* C, int ldc, hipStream_t stream);
+template <typename H>
+int launch_gemm_half(int M, int N, int K, const H* Ah, int lda_h, const H* Bh, int ldb_h, const float* rs,
+                     const float* cs, float* C, int ldc, hipStream_t stream);
+int launch_probe_mfma_f64(double* out, hipStream_t stream);
+
+// ---- solves and refinement (solve.hip) ----
+// x (n x nrhs, ld) <- P x using per-chunk moves from launch_chunk_moves
+template <typename T>
+int launch_apply_chunk_moves(T* X, long long ldx, int n, int nrhs, int W, const int* moves, hipStream_t stream);
+// triangular solves with the packed LU factor; flags: int[nblocks] epoch flags
+template <typename T>
+int launch_trsv_lower_unit(const T* LU, long long lda, int n, T* x, int* flags, int epoch, unsigned* err,
+                           long long spin_limit, hipStream_t stream);
+template <typename T>
+int launch_trsv_upper(const T* LU, long long lda, int n, T* x, int* flags, int epoch, unsigned* err,
+                      long long spin_limit, hipStream_t stream);
+int trsv_block_rows();
+
+// IR building blocks (FP64 residual side)
+int launch_residual(const double* A, long long lda, int n, const double* x, const double* b, double* r,
+                    double* partial, int splits, hipStream_t stream);
+int launch_row_abs_sums(const double* A, long long lda, int n, double* partial, int splits, double* out_max,
+                        hipStream_t stream);
+int launch_amax(const double* x, int n, unsigned long long* out_bits, hipStream_t stream);
+int launch_convert_f64_f32(const double* src, long long lds, float* dst, long long ldd, int rows, int cols,
+                           hipStream_t stream);
+int launch_axpy_f32_to_f64(double* x, const float* d, int n, hipStream_t stream);
+int launch_copy_f64(const double* src, long long lds, double* dst, long long ldd, int rows, int cols,
+                    hipStream_t stream);
+int launch_fill_zero(void* p, size_t bytes, hipStream_t stream);
+
+// selector network (mlp.hip)
+int launch_mlp_forward(const float* theta, const float* X, int batch, float* logits, hipStream_t stream);
+int launch_mlp_train(float* theta, float* m, float* v, const float* X, const int* Y, int batch, int epochs,
+                     float lr, int t0, float* loss_out, float* grad_out, int update, hipStream_t stream);
+
+}  // namespace lu

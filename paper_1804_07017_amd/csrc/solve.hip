@@ -1,0 +1,344 @@
+// Solves with the packed LU factor (LAPACK getrs semantics: x = U^-1 L^-1 P b)
+// and the FP64 side of iterative refinement.
+//
+// Triangular solves are "sync-free": one work-group per 64-row block, launched
+// in block order.  Block r accumulates L(r, c) x(c) for every finished block
+// c < r as soon as c's ready flag shows the current epoch, then solves its
+// 64 x 64 diagonal block in one wave and publishes x(r) with a release store
+// of its flag.  A work-group only waits for lower-numbered blocks, which the
+// hardware dispatched before it, so the grid always makes progress; every wait
+// is bounded by a wall-clock limit that sets an error word instead of hanging.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace lu {
+
+namespace {
+
+constexpr int kRB = 64;          // rows per triangular block
+constexpr int kThreads = 256;    // 4 column groups x 64 rows
+
+__device__ __forceinline__ bool wait_flag(const int* flag, int epoch, unsigned* err, long long limit) {
+    __shared__ int s_fail;
+    if (threadIdx.x == 0) {
+        int fail = 0;
+        const long long t0 = wall_clock64();
+        while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) { fail = 1; break; }
+            if (wall_clock64() - t0 > limit) {
+                __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                fail = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        s_fail = fail;
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return s_fail != 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void trsv_lower_unit_kernel(const T* __restrict__ LU, long long lda, int n,
+                                                                    T* __restrict__ x, int* flags, int epoch,
+                                                                    unsigned* err, long long limit) {
+    __shared__ T part[4][kRB];
+    const int r = blockIdx.x;
+    const int tid = threadIdx.x, i = tid % kRB, g = tid / kRB;
+    const int row = r * kRB + i;
+    T acc = T(0);
+    for (int cb = 0; cb < r; ++cb) {
+        if (wait_flag(&flags[cb], epoch, err, limit)) return;
+        if (row < n) {
+            const int j0 = cb * kRB;
+#pragma unroll 4
+            for (int jj = g; jj < kRB; jj += 4) acc += LU[row + (long long)(j0 + jj) * lda] * x[j0 + jj];
+        }
+    }
+    part[g][i] = acc;
+    __syncthreads();
+    if (tid < kRB) {
+        T y = (row < n) ? x[row] - ((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) : T(0);
+        const int nb = min(kRB, n - r * kRB);
+        for (int s = 0; s < nb; ++s) {
+            const T xs = __shfl(y, s, kWave);
+            if (i > s && row < n) y -= LU[row + (long long)(r * kRB + s) * lda] * xs;
+        }
+        if (row < n) x[row] = y;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    }
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(&flags[r], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void trsv_upper_kernel(const T* __restrict__ LU, long long lda, int n,
+                                                               T* __restrict__ x, int* flags, int epoch,
+                                                               unsigned* err, long long limit) {
+    __shared__ T part[4][kRB];
+    const int nblk = (n + kRB - 1) / kRB;
+    const int r = nblk - 1 - (int)blockIdx.x;         // bottom block first
+    const int tid = threadIdx.x, i = tid % kRB, g = tid / kRB;
+    const int row = r * kRB + i;
+    T acc = T(0);
+    for (int cb = nblk - 1; cb > r; --cb) {
+        if (wait_flag(&flags[cb], epoch, err, limit)) return;
+        if (row < n) {
+            const int j0 = cb * kRB;
+            const int nj = min(kRB, n - j0);
+#pragma unroll 4
+            for (int jj = g; jj < nj; jj += 4) acc += LU[row + (long long)(j0 + jj) * lda] * x[j0 + jj];
+        }
+    }
+    part[g][i] = acc;
+    __syncthreads();
+    if (tid < kRB) {
+        T y = (row < n) ? x[row] - ((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) : T(0);
+        const int nb = min(kRB, n - r * kRB);
+        for (int s = nb - 1; s >= 0; --s) {
+            T xs = T(0);
+            if (i == s) { y = y / LU[row + (long long)row * lda]; }
+            xs = __shfl(y, s, kWave);
+            if (i < s) y -= LU[row + (long long)(r * kRB + s) * lda] * xs;
+        }
+        if (row < n) x[row] = y;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    }
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(&flags[r], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// P x for each right-hand side: chunk c's interchanges, chunks in order.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void apply_chunk_moves_kernel(T* X, long long ldx, int n, int W,
+                                                                      const int* moves) {
+    T* x = X + (long long)blockIdx.x * ldx;
+    const int nchunk = (n + W - 1) / W;
+    const int tid = threadIdx.x;
+    constexpr int kPer = (2 * kMovesMaxW + kThreads - 1) / kThreads;
+    for (int c = 0; c < nchunk; ++c) {
+        const int* mv = moves + (size_t)c * kMovesLen;
+        const int base = c * W;
+        const int ntop = mv[0], nex = mv[1];
+        T v[kPer];
+        int dst[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int s = tid + u * kThreads;
+            dst[u] = -1;
+            if (s < ntop) { dst[u] = mv[2 + 2 * s]; v[u] = x[base + mv[3 + 2 * s]]; }
+            else if (s < ntop + nex) {
+                const int e = s - ntop;
+                dst[u] = mv[kMovesExtra + 2 * e];
+                v[u] = x[base + mv[kMovesExtra + 1 + 2 * e]];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kPer; ++u)
+            if (dst[u] >= 0) x[base + dst[u]] = v[u];
+        __syncthreads();
+    }
+}
+
+// partial[s][i] = sum over columns of slice s of A[i,j] * x[j]   (x == nullptr: |A[i,j]|)
+__global__ __launch_bounds__(256) void gemv_partial_kernel(const double* __restrict__ A, long long lda, int n,
+                                                           const double* __restrict__ x, double* partial,
+                                                           int splits) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int s = blockIdx.y;
+    const int per = (n + splits - 1) / splits;
+    const int j0 = s * per, j1 = min(n, j0 + per);
+    double acc = 0.0;
+    if (i < n) {
+        if (x) {
+#pragma unroll 8
+            for (int j = j0; j < j1; ++j) acc += A[i + (long long)j * lda] * x[j];
+        } else {
+#pragma unroll 8
+            for (int j = j0; j < j1; ++j) acc += fabs(A[i + (long long)j * lda]);
+        }
+        partial[(long long)s * n + i] = acc;
+    }
+}
+
+__device__ __forceinline__ void atomic_max_abs(unsigned long long* out, double v) {
+    // non-negative doubles order like their bit patterns; NaN bits sort above +inf
+    atomicMax(out, (unsigned long long)__double_as_longlong(fabs(v)));
+}
+
+__global__ __launch_bounds__(256) void residual_finish_kernel(const double* partial, int splits, int n,
+                                                              const double* b, double* r) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) {
+        double s = 0.0;
+        for (int p = 0; p < splits; ++p) s += partial[(long long)p * n + i];
+        r[i] = b[i] - s;
+    }
+}
+
+__global__ __launch_bounds__(256) void rowsum_max_kernel(const double* partial, int splits, int n,
+                                                         unsigned long long* out) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) {
+        double s = 0.0;
+        for (int p = 0; p < splits; ++p) s += partial[(long long)p * n + i];
+        atomic_max_abs(out, s);
+    }
+}
+
+__global__ __launch_bounds__(256) void amax_kernel(const double* x, int n, unsigned long long* out) {
+    __shared__ double red[256];
+    double m = 0.0;
+    bool bad = false;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        const double a = fabs(x[i]);
+        if (!(a <= 1.7976931348623157e308)) bad = true;
+        m = fmax(m, a);
+    }
+    red[threadIdx.x] = bad ? __longlong_as_double(0x7ff8000000000000LL) : m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long best = 0ull;
+        for (int t = 0; t < 256; ++t) {
+            const unsigned long long bits = (unsigned long long)__double_as_longlong(fabs(red[t]));
+            best = bits > best ? bits : best;
+        }
+        atomicMax(out, best);
+    }
+}
+
+__global__ __launch_bounds__(256) void convert_kernel(const double* src, long long lds, float* dst, long long ldd,
+                                                      int rows, int cols) {
+    const long long total = (long long)rows * cols;
+    for (long long e = blockIdx.x * 256ll + threadIdx.x; e < total; e += (long long)gridDim.x * 256) {
+        const int i = (int)(e % rows);
+        const long long j = e / rows;
+        dst[i + j * ldd] = (float)src[i + j * lds];
+    }
+}
+
+__global__ __launch_bounds__(256) void copy_kernel(const double* src, long long lds, double* dst, long long ldd,
+                                                   int rows, int cols) {
+    const long long total = (long long)rows * cols;
+    for (long long e = blockIdx.x * 256ll + threadIdx.x; e < total; e += (long long)gridDim.x * 256) {
+        const int i = (int)(e % rows);
+        const long long j = e / rows;
+        dst[i + j * ldd] = src[i + j * lds];
+    }
+}
+
+__global__ __launch_bounds__(256) void axpy_kernel(double* x, const float* d, int n) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) x[i] = x[i] + (double)d[i];
+}
+
+__global__ __launch_bounds__(256) void fill_zero_kernel(unsigned* p, size_t words) {
+    for (size_t e = blockIdx.x * 256ull + threadIdx.x; e < words; e += (size_t)gridDim.x * 256) p[e] = 0u;
+}
+
+inline int grid_for(long long work) {
+    long long g = (work + 255) / 256;
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+}  // namespace
+
+int trsv_block_rows() { return kRB; }
+
+template <typename T>
+int launch_apply_chunk_moves(T* X, long long ldx, int n, int nrhs, int W, const int* moves, hipStream_t stream) {
+    if (n <= 0 || nrhs <= 0) return 0;
+    hipLaunchKernelGGL((apply_chunk_moves_kernel<T>), dim3(nrhs), dim3(kThreads), 0, stream, X, ldx, n, W, moves);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <typename T>
+int launch_trsv_lower_unit(const T* LU, long long lda, int n, T* x, int* flags, int epoch, unsigned* err,
+                           long long spin_limit, hipStream_t stream) {
+    if (n <= 0) return 0;
+    const int nblk = (n + kRB - 1) / kRB;
+    hipLaunchKernelGGL((trsv_lower_unit_kernel<T>), dim3(nblk), dim3(kThreads), 0, stream, LU, lda, n, x, flags,
+                       epoch, err, spin_limit);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <typename T>
+int launch_trsv_upper(const T* LU, long long lda, int n, T* x, int* flags, int epoch, unsigned* err,
+                      long long spin_limit, hipStream_t stream) {
+    if (n <= 0) return 0;
+    const int nblk = (n + kRB - 1) / kRB;
+    hipLaunchKernelGGL((trsv_upper_kernel<T>), dim3(nblk), dim3(kThreads), 0, stream, LU, lda, n, x, flags, epoch,
+                       err, spin_limit);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_residual(const double* A, long long lda, int n, const double* x, const double* b, double* r,
+                    double* partial, int splits, hipStream_t stream) {
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(gemv_partial_kernel, dim3((n + 255) / 256, splits), dim3(256), 0, stream, A, lda, n, x,
+                       partial, splits);
+    hipLaunchKernelGGL(residual_finish_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, partial, splits, n, b,
+                       r);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_row_abs_sums(const double* A, long long lda, int n, double* partial, int splits, double* out_max,
+                        hipStream_t stream) {
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(gemv_partial_kernel, dim3((n + 255) / 256, splits), dim3(256), 0, stream, A, lda, n,
+                       (const double*)nullptr, partial, splits);
+    hipLaunchKernelGGL(rowsum_max_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, partial, splits, n,
+                       reinterpret_cast<unsigned long long*>(out_max));
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_amax(const double* x, int n, unsigned long long* out_bits, hipStream_t stream) {
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(amax_kernel, dim3(min(1024, (n + 255) / 256)), dim3(256), 0, stream, x, n, out_bits);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_convert_f64_f32(const double* src, long long lds, float* dst, long long ldd, int rows, int cols,
+                           hipStream_t stream) {
+    hipLaunchKernelGGL(convert_kernel, dim3(grid_for((long long)rows * cols)), dim3(256), 0, stream, src, lds, dst,
+                       ldd, rows, cols);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_copy_f64(const double* src, long long lds, double* dst, long long ldd, int rows, int cols,
+                    hipStream_t stream) {
+    hipLaunchKernelGGL(copy_kernel, dim3(grid_for((long long)rows * cols)), dim3(256), 0, stream, src, lds, dst, ldd,
+                       rows, cols);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_axpy_f32_to_f64(double* x, const float* d, int n, hipStream_t stream) {
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(axpy_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, x, d, n);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_fill_zero(void* p, size_t bytes, hipStream_t stream) {
+    const size_t words = bytes / 4;
+    if (words == 0) return 0;
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for((long long)words)), dim3(256), 0, stream,
+                       reinterpret_cast<unsigned*>(p), words);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template int launch_apply_chunk_moves<double>(double*, long long, int, int, int, const int*, hipStream_t);
+template int launch_apply_chunk_moves<float>(float*, long long, int, int, int, const int*, hipStream_t);
+template int launch_trsv_lower_unit<double>(const double*, long long, int, double*, int*, int, unsigned*, long long,
+                                            hipStream_t);
+template int launch_trsv_lower_unit<float>(const float*, long long, int, float*, int*, int, unsigned*, long long,
+                                           hipStream_t);
+template int launch_trsv_upper<double>(const double*, long long, int, double*, int*, int, unsigned*, long long,
+                                       hipStream_t);
+template int launch_trsv_upper<float>(const float*, long long, int, float*, int*, int, unsigned*, long long,
+                                      hipStream_t);
+
+}  // namespace lu

@@ -1,0 +1,57 @@
+// Library-owned per-device state: the panel stream, events, workspace.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <vector>
+
+#include "plan.hpp"
+
+namespace lu {
+
+#define LU_HIP(call)                                   \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess) return LU_ERR_HIP;       \
+    } while (0)
+
+struct Buffer {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+// Grow-only device allocation; returns 0 or LU_ERR_NOMEM.
+int ensure(Buffer& b, size_t bytes);
+void release(Buffer& b);
+
+struct DeviceState {
+    int dev = -1;
+    int num_cus = 0;
+    long long spin_limit = 0;          // ~2 s of the device wall clock
+    hipStream_t panel_stream = nullptr;
+    std::vector<hipEvent_t> events;    // ring used for cross-stream dependencies
+    int ev_next = 0;
+
+    // panel barrier words: 2 slots x (counter, error); slot alternates per launch
+    unsigned* sync = nullptr;
+    int sync_slot = 0;
+    Buffer cand;                       // candidate exchange area of the panel kernel
+    Buffer moves;                      // per-panel composed interchanges
+    int* info = nullptr;               // library INFO word
+    hipStream_t last_stream = nullptr; // stream of the last factorization
+    int* last_info = nullptr;
+
+    // mixed precision operand copies
+    Buffer lh, uh, rs, cs;
+    // solves / refinement
+    Buffer solve_moves, flags, partial, ir_r, ir_x32, ir_a32, ir_a64, ir_norms, ir_ipiv, ir_b;
+    int trsv_epoch = 0;
+
+    std::map<long long, std::vector<PlanTask>> plans;
+};
+
+DeviceState* device_state(int* err);
+void release_all();
+int panel_wgs_for(const DeviceState& s, int m, int panel_cus);
+
+}  // namespace lu

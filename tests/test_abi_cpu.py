@@ -1,0 +1,202 @@
+"""Host-side checks of the native library (no GPU): it loads, exports every
+symbol the headers declare, rejects illegal arguments before touching the
+device, and the schedule planner builds sound look-ahead task graphs."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1804_07017_amd as lu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if not h.endswith(".h"):
+            continue
+        txt = open(os.path.join(ROOT, "include", h)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        for m in re.finditer(r"^\s*(?:int|void)\s+(lu_\w+)\s*\(", txt, flags=re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lu.load()
+    declared = _declared_symbols()
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(lu.exported_symbols())
+
+
+def test_argument_errors_before_any_device_call():
+    lib = lu.load()
+    assert lib.lu_factor(-1, None, 1, None, None) == -1
+    assert lib.lu_factor(4, None, 4, None, None) == -2
+    assert lib.lu_factor(4, 8, 3, 8, None) == -3
+    assert lib.lu_factor(4, 8, 4, None, None) == -4
+    assert lib.lu_factor(0, None, 1, None, None) == 0
+    assert lib.lu_factor_ex(4, 8, 4, 7, 8, None, None, None) == -5
+    bad = lu.Schedule(100, 1, 16)
+    import ctypes
+    assert lib.lu_factor_ex(4, 8, 4, 0, 8, ctypes.byref(bad), None, None) == -6
+    bad = lu.Schedule(64, 3, 16)
+    assert lib.lu_factor_ex(4, 8, 4, 0, 8, ctypes.byref(bad), None, None) == -6
+    assert lib.lu_solve(-1, 1, None, None, None) == -1
+    assert lib.lu_solve(4, -1, None, None, None) == -2
+    assert lib.lu_solve_ex(4, 1, 8, 2, 8, 8, 4, None) == -4
+    assert lib.lu_solve_ex(4, 1, 8, 4, 8, 8, 2, None) == -7
+    it = ctypes.c_int(0)
+    res = ctypes.c_double(0)
+    assert lib.lu_solve_ir(4, 1, 8, 4, 8, 4, 8, 4, 9, 5, ctypes.byref(it), ctypes.byref(res), None) == -9
+    assert lib.lu_solve_ir(4, 1, 8, 4, 8, 4, 8, 4, 2, 0, ctypes.byref(it), ctypes.byref(res), None) == -10
+    assert lib.lu_solve_ir(0, 1, None, 1, None, 1, None, 1, 2, 5, ctypes.byref(it), ctypes.byref(res), None) == 0
+    assert lib.lu_k_panel(0, 4, 8, 8, 4, 8, 0, None, None) == -3
+    assert lib.lu_k_gemm(0, 4, 4, 4, 8, 2, 8, 4, 8, 4, None) == -6
+
+
+def test_selector_file_errors(tmp_path):
+    assert lu.lu_selector_load(tmp_path / "missing.bin") < 0
+    p = tmp_path / "bad.bin"
+    p.write_bytes(b"not a weights file")
+    assert lu.lu_selector_load(p) < 0
+
+
+# ------------------------------------------------------------- plan checks
+def _access(t, b, n):
+    """(write columns, read columns, ipiv written, ipiv read) of a task."""
+    w = set(range(t["col_begin"], t["col_end"]))
+    r = set()
+    ipw = ipr = None
+    if t["kind"] == lu.LU_TASK_PANEL:
+        ipw = t["step"]
+    elif t["kind"] == lu.LU_TASK_UPDATE:
+        k = t["step"]
+        r = set(range(k * b, min(n, k * b + b)))
+        ipr = k
+    else:
+        ipr = t["step"]
+    return w, r, ipw, ipr
+
+
+def _happens_before(tasks):
+    T = len(tasks)
+    before = [set() for _ in range(T)]
+    last = {0: None, 1: None}
+    for i, t in enumerate(tasks):
+        s = t["stream"]
+        if last[s] is not None:
+            before[i] |= before[last[s]] | {last[s]}
+        for wv in t["waits"]:
+            before[i] |= before[wv] | {wv}
+        last[s] = i
+    return before
+
+
+@pytest.mark.parametrize("n,b,depth", [(10, 4, 0), (10, 4, 1), (13, 4, 2), (64, 16, 1), (70, 16, 2),
+                                       (33, 8, 2), (8, 8, 1), (5, 8, 2), (100, 32, 1)])
+def test_plan_is_race_free_and_complete(n, b, depth):
+    rc, tasks = lu.lu_plan_build(n, b, depth)
+    assert rc == len(tasks) > 0
+    N = (n + b - 1) // b
+    # every panel factored once; every (step, column) pair of the trailing
+    # matrix updated exactly once; every left swap applied once
+    panels = [t["step"] for t in tasks if t["kind"] == lu.LU_TASK_PANEL]
+    assert sorted(panels) == list(range(N))
+    cover = {}
+    for t in tasks:
+        if t["kind"] == lu.LU_TASK_UPDATE:
+            for c in range(t["col_begin"], t["col_end"]):
+                cover[(t["step"], c)] = cover.get((t["step"], c), 0) + 1
+    for k in range(N):
+        for c in range(min(n, (k + 1) * b), n):
+            assert cover.get((k, c)) == 1, (k, c)
+    assert len(cover) == sum(max(0, n - min(n, (k + 1) * b)) for k in range(N))
+    if depth == 0:
+        assert all(t["stream"] == 0 for t in tasks)
+    else:
+        assert all(t["stream"] == 1 for t in tasks if t["kind"] == lu.LU_TASK_PANEL)
+    # race freedom: tasks not ordered by happens-before touch disjoint data
+    hb = _happens_before(tasks)
+    acc = [_access(t, b, n) for t in tasks]
+    for i in range(len(tasks)):
+        for j in range(i):
+            if j in hb[i]:
+                continue
+            wi, ri, pwi, pri = acc[i]
+            wj, rj, pwj, prj = acc[j]
+            assert not (wi & wj) and not (wi & rj) and not (ri & wj), (tasks[j], tasks[i])
+            assert pwi is None or (pwi != prj and pwi != pwj)
+            assert pwj is None or pwj != pri
+
+
+def _run_task(A, ipiv, t, b, n):
+    """Execute one plan task on the numpy matrix A (FP64) in place."""
+    k = t["step"]
+    c0, c1 = t["col_begin"], t["col_end"]
+    if t["kind"] == lu.LU_TASK_PANEL:
+        j0, j1 = c0, c1
+        for d in range(j0, j1):
+            p = d + int(np.argmax(np.abs(A[d:, d])))
+            ipiv[d] = p
+            if p != d:
+                A[[d, p], j0:j1] = A[[p, d], j0:j1]
+            if A[d, d] != 0:
+                A[d + 1:, d] /= A[d, d]
+            A[d + 1:, d + 1:j1] -= np.outer(A[d + 1:, d], A[d, d + 1:j1])
+    elif t["kind"] == lu.LU_TASK_UPDATE:
+        kb, w = k * b, min(b, n - k * b)
+        for d in range(kb, kb + w):
+            p = ipiv[d]
+            if p != d:
+                A[[d, p], c0:c1] = A[[p, d], c0:c1]
+        L11 = np.tril(A[kb:kb + w, kb:kb + w], -1) + np.eye(w)
+        A[kb:kb + w, c0:c1] = np.linalg.solve(L11, A[kb:kb + w, c0:c1])
+        A[kb + w:, c0:c1] -= A[kb + w:, kb:kb + w] @ A[kb:kb + w, c0:c1]
+    else:
+        kb, w = k * b, min(b, n - k * b)
+        for d in range(kb, kb + w):
+            p = ipiv[d]
+            if p != d:
+                A[[d, p], c0:c1] = A[[p, d], c0:c1]
+
+
+def _random_legal_order(tasks, rng):
+    q = {0: [i for i, t in enumerate(tasks) if t["stream"] == 0],
+         1: [i for i, t in enumerate(tasks) if t["stream"] == 1]}
+    done = set()
+    order = []
+    while q[0] or q[1]:
+        ready = [s for s in (0, 1) if q[s] and all(w in done for w in tasks[q[s][0]]["waits"])]
+        assert ready, "plan deadlocks"
+        s = ready[rng.integers(len(ready))]
+        i = q[s].pop(0)
+        done.add(i)
+        order.append(i)
+    return order
+
+
+@pytest.mark.parametrize("n,b,depth", [(24, 4, 1), (30, 8, 2), (37, 8, 1), (37, 8, 2), (40, 8, 0)])
+def test_plan_executes_to_the_oracle_result_in_any_legal_order(n, b, depth):
+    import oracle
+    import synth
+    A0 = np.array(synth.uniform(n, seed=n), order="F")
+    rc, tasks = lu.lu_plan_build(n, b, depth)
+    results = []
+    rng = np.random.default_rng(0)
+    for trial in range(4):
+        A = A0.copy()
+        ipiv = np.zeros(n, dtype=np.int64)
+        order = range(len(tasks)) if trial == 0 else _random_legal_order(tasks, rng)
+        for i in order:
+            _run_task(A, ipiv, tasks[i], b, n)
+        results.append((A, ipiv))
+    for A, ipiv in results[1:]:
+        assert np.array_equal(A, results[0][0]) and np.array_equal(ipiv, results[0][1])
+    LU, ip, info = oracle.getrf(A0)
+    assert np.array_equal(results[0][1], ip)
+    assert np.abs(results[0][0] - LU).max() <= 1e-10 * max(1.0, np.abs(LU).max())

@@ -1,0 +1,179 @@
+"""End-to-end parity of lu_factor / lu_factor_ex / lu_solve on the GPU against
+the CPU oracle (element by element where the oracle runs in seconds) and
+against properties that hold at any size (scaled residuals, planted factors)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import pins
+
+pytestmark = pytest.mark.gpu
+
+
+def _factor(gpu, A_np, b, depth, panel_cus=16, prec=0, lda=None):
+    import torch
+    n = A_np.shape[0]
+    dt = torch.float64 if prec == 0 else torch.float32
+    dA = gpu.to_device(np.asarray(A_np), dt, lda=lda)
+    ipiv = torch.zeros(max(n, 1), dtype=torch.int32, device="cuda")
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    rc = gpu.lu_factor_ex(dA, ipiv, prec=prec, sched=(b, depth, panel_cus), d_info=info)
+    assert rc == 0
+    torch.cuda.synchronize()
+    rc2, _ = gpu.lu_factor_info()
+    assert rc2 == 0
+    return gpu.to_host(dA).astype(np.float64), ipiv.cpu().numpy()[:n], int(info.item())
+
+
+def test_c1_512_b64_depth0_matches_oracle(gpu):
+    A = synth.uniform(512, seed=1)
+    LU, ipiv, info = _factor(gpu, A, 64, 0)
+    oLU, oip, oinfo = oracle.getrf(A, nthreads=8)
+    assert info == oinfo == 0
+    assert np.array_equal(ipiv, oip)
+    assert np.abs(LU - oLU).max() <= 1e-12 * np.abs(oLU).max()
+    assert oracle.r_factor(A, LU, ipiv) <= 16.0
+
+
+@pytest.mark.parametrize("n,b,depth,lda", [(1000, 64, 1, None), (1000, 128, 2, 1003), (1, 64, 1, None),
+                                           (37, 64, 0, 40), (65, 32, 2, None), (777, 256, 1, None),
+                                           (1536, 512, 2, None), (300, 128, 0, 301)])
+def test_ragged_and_schedules_match_oracle(gpu, n, b, depth, lda):
+    A = synth.uniform(n, seed=n + b)
+    LU, ipiv, info = _factor(gpu, A, b, depth, lda=lda)
+    oLU, oip, _ = oracle.getrf(A, nthreads=8)
+    gap_ok = True
+    assert np.array_equal(ipiv, oip) or not gap_ok
+    assert np.abs(LU - oLU).max() <= 1e-11 * max(1.0, np.abs(oLU).max())
+    assert oracle.r_factor(A, LU, ipiv) <= 16.0
+
+
+def test_lda_padding_untouched(gpu):
+    import torch
+    n, lda = 300, 311
+    A = synth.uniform(n, seed=3)
+    dA = gpu.to_device(A, lda=lda)
+    base = dA.t()  # (n, lda) storage view
+    full = torch.as_strided(dA, (lda, n), (1, lda))
+    full[n:, :] = 12345.0
+    ipiv = torch.zeros(n, dtype=torch.int32, device="cuda")
+    assert gpu.lu_factor(dA, ipiv) == 0
+    torch.cuda.synchronize()
+    assert bool((full[n:, :] == 12345.0).all())
+    del base
+
+
+def test_schedule_invariance_bitwise(gpu):
+    n, b = 1500, 128
+    A = synth.uniform(n, seed=21)
+    ref = None
+    for depth in (0, 1, 2):
+        for cus in (8, 16, 32):
+            LU, ipiv, _ = _factor(gpu, A, b, depth, cus)
+            if ref is None:
+                ref = (LU, ipiv)
+            else:
+                assert np.array_equal(LU, ref[0]) and np.array_equal(ipiv, ref[1]), (depth, cus)
+
+
+def test_zero_column_and_zero_matrix_info(gpu):
+    A = synth.uniform(200, seed=5)
+    A[:, 70] = 0.0
+    _, _, info = _factor(gpu, A, 64, 1)
+    _, _, oinfo = oracle.getrf(A)
+    assert info == oinfo == 71
+    LU, ipiv, info = _factor(gpu, np.zeros((130, 130), order="F"), 64, 1)
+    assert info == 1 and np.array_equal(ipiv, np.arange(130))
+
+
+def test_identity_and_permutation(gpu):
+    n = 257
+    LU, ipiv, _ = _factor(gpu, np.eye(n, order="F"), 64, 1)
+    assert np.array_equal(LU, np.eye(n)) and np.array_equal(ipiv, np.arange(n))
+    perm = synth.rng(9, 2).permutation(n)
+    A = np.asfortranarray(np.eye(n)[perm, :])
+    LU, ipiv, _ = _factor(gpu, A, 64, 2)
+    assert np.array_equal(LU, np.eye(n))
+    assert np.array_equal(A[oracle.perm_from_ipiv(ipiv), :], np.eye(n))
+
+
+@pytest.mark.parametrize("n", [512, 2000])
+def test_planted_factors_recovered(gpu, n):
+    A, L, U, perm = synth.planted(n, seed=4)
+    LU, ipiv, _ = _factor(gpu, A, 128, 1)
+    assert np.array_equal(ipiv, pins.planted_ipiv(perm))
+    Lh, Uh = oracle.unpack(LU)
+    assert np.abs(Lh - L).max() <= 1e-12
+    assert np.abs(Uh - U).max() <= 1e-12 * np.abs(U).max()
+
+
+@pytest.mark.parametrize("n,nrhs", [(512, 1), (2000, 3), (100, 1)])
+def test_solve_matches_oracle(gpu, n, nrhs):
+    import torch
+    A = synth.uniform(n, seed=n)
+    B = synth.rhs(n, seed=n, nrhs=nrhs)
+    LU, ipiv, _ = _factor(gpu, A, 128, 1)
+    dLU = gpu.to_device(LU)
+    dp = torch.tensor(ipiv, dtype=torch.int32, device="cuda")
+    dB = gpu.to_device(B)
+    assert gpu.lu_solve_ex(dLU, dp, dB) == 0
+    torch.cuda.synchronize()
+    X = gpu.to_host(dB)
+    oLU, oip, _ = oracle.getrf(A, nthreads=8)
+    Xo = oracle.getrs(oLU, oip, B)
+    for c in range(nrhs):
+        assert oracle.r_hpl(A, X[:, c], B[:, c]) <= 16.0
+    assert np.abs(X - Xo).max() <= 1e-8 * np.abs(Xo).max()
+
+
+def test_solve_north_star_form(gpu):
+    import torch
+    n = 333
+    A = synth.uniform(n, seed=2)
+    b = synth.rhs(n, seed=2)
+    dA = gpu.to_device(A)
+    dp = torch.zeros(n, dtype=torch.int32, device="cuda")
+    assert gpu.lu_factor(dA, dp) == 0
+    torch.cuda.synchronize()
+    db = gpu.to_device(b)
+    assert gpu.lu_solve(dA, dp, db) == 0
+    x = gpu.to_host(db)[:, 0]
+    assert oracle.r_hpl(A, x, b[:, 0]) <= 16.0
+
+
+def test_fp32_factor_residual(gpu):
+    n = 1000
+    A = synth.uniform(n, seed=8)
+    LU, ipiv, _ = _factor(gpu, A, 128, 1, prec=1)
+    L, U = oracle.unpack(LU)
+    A32 = A.astype(np.float32).astype(np.float64)
+    r = np.linalg.norm(A32[oracle.perm_from_ipiv(ipiv)] - L @ U) / (np.linalg.norm(A32) * n * 2.0 ** -24)
+    assert r <= 16.0
+
+
+def test_c2_8192_lookahead_and_solve(gpu):
+    import torch
+    n = 8192
+    A = synth.uniform(n, seed=1)
+    b = synth.rhs(n, seed=1)
+    for bs in (128, 256):
+        dA = gpu.to_device(A)
+        ipiv = torch.zeros(n, dtype=torch.int32, device="cuda")
+        assert gpu.lu_factor_ex(dA, ipiv, sched=(bs, 1, 16)) == 0
+        torch.cuda.synchronize()
+        assert gpu.lu_factor_info() == (0, 0)
+        # scaled factor residual with a library GEMM (rocBLAS via torch) on the device
+        L = torch.tril(dA, -1) + torch.eye(n, dtype=torch.float64, device="cuda")
+        U = torch.triu(dA)
+        perm = torch.tensor(oracle.perm_from_ipiv(ipiv.cpu().numpy()), device="cuda")
+        dA0 = gpu.to_device(A)
+        R = dA0[perm, :] - L @ U
+        rf = (torch.linalg.norm(R) / (torch.linalg.norm(dA0) * n * 2.0 ** -53)).item()
+        assert rf <= 16.0, rf
+        del L, U, R, dA0
+        db = gpu.to_device(b)
+        assert gpu.lu_solve_ex(dA, ipiv, db) == 0
+        torch.cuda.synchronize()
+        x = gpu.to_host(db)[:, 0]
+        assert oracle.r_hpl(A, x, b[:, 0]) <= 16.0
