@@ -31,9 +31,20 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 constexpr int kBM = 128, kBN = 128, kThreads = 256;
 
+// Accumulator type and output lane layout of the 16x16 MFMA result D (16 x 16):
+// lane l, register r holds D[row(l, r)][l % 16] with
+//   v_mfma_f64_16x16x4f64:   row = l/16 + 4r   (measured on gfx950)
+//   v_mfma_f32_16x16x4f32:   row = 4(l/16) + r
+// With the swapped operand roles, D's rows run along C's columns.
 template <typename T> struct Acc;
-template <> struct Acc<double> { typedef v4d type; };
-template <> struct Acc<float> { typedef v4f type; };
+template <> struct Acc<double> {
+    typedef v4d type;
+    static __device__ __forceinline__ int col(int lg, int r) { return lg + 4 * r; }
+};
+template <> struct Acc<float> {
+    typedef v4f type;
+    static __device__ __forceinline__ int col(int lg, int r) { return 4 * lg + r; }
+};
 
 __device__ __forceinline__ v4d mfma(double a, double b, v4d c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -81,7 +92,7 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_nn_sub(int M, int N, int K, 
         for (int cb = 0; cb < 4; ++cb) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int col = n0 + wn * 64 + cb * 16 + 4 * lg + r;
+                const int col = n0 + wn * 64 + cb * 16 + Acc<T>::col(lg, r);
                 acc[rb][cb][r] = (row < M && col < N) ? C[row + (long long)col * ldc] : T(0);
             }
         }
@@ -148,7 +159,7 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_nn_sub(int M, int N, int K, 
             for (int cb = 0; cb < 4; ++cb) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int col = n0 + wn * 64 + cb * 16 + 4 * lg + r;
+                    const int col = n0 + wn * 64 + cb * 16 + Acc<T>::col(lg, r);
                     if (col < N) C[row + (long long)col * ldc] = acc[rb][cb][r];
                 }
             }
