@@ -93,6 +93,8 @@ DeviceState* device_state(int* err) {
     if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || rate_khz <= 0)
         rate_khz = 100000;
     s->spin_limit = (long long)rate_khz * 1000ll * 2;   // 2 seconds
+    s->panel_occupancy = 1;
+    if (const char* e = std::getenv("LU_PANEL_OCC")) s->panel_occupancy = std::atoi(e) == 2 ? 2 : 1;
     if (const char* e = std::getenv("LU_DEBUG_BARRIER_SPIN")) {
         long long v = std::atoll(e);
         if (v > 0) s->spin_limit = v;                    // debug knob: tiny bound forces the timeout path
@@ -107,10 +109,9 @@ DeviceState* device_state(int* err) {
     if (hipMemset(s->sync, 0, 8 * sizeof(unsigned)) != hipSuccess) { *err = LU_ERR_HIP; return nullptr; }
     if (hipMalloc(&s->info, 4 * sizeof(int)) != hipSuccess) { *err = LU_ERR_NOMEM; return nullptr; }
     if (hipMemset(s->info, 0, 4 * sizeof(int)) != hipSuccess) { *err = LU_ERR_HIP; return nullptr; }
-    // candidate area sized for double and the maximum work-group count
-    size_t cand = 2 * kMaxCand * sizeof(double) + 2 * kMaxCand * sizeof(int) + 2 * kMaxCand * kNB * sizeof(double) +
-                  2 * kNB * sizeof(double) + 256;
-    if (ensure(s->cand, cand)) { *err = LU_ERR_NOMEM; return nullptr; }
+    // tagged exchange area of the panel kernel (sized for FP64 and the maximum work-group count)
+    if (ensure(s->cand, (size_t)kPanelXchWords * sizeof(unsigned long long))) { *err = LU_ERR_NOMEM; return nullptr; }
+    if (hipMemset(s->cand.ptr, 0, s->cand.bytes) != hipSuccess) { *err = LU_ERR_HIP; return nullptr; }
     g_states[dev] = s;
     return s;
 }
@@ -134,13 +135,15 @@ void release_all() {
 }
 
 int panel_wgs_for(const DeviceState& s, int m, int panel_cus) {
-    const int per = panel_max_rows_per_wg();
-    int need = (m + per - 1) / per;
-    int wgs = std::max(need, std::max(1, panel_cus));
-    // at least one row block per work-group is useful; never more groups than rows/64
-    int useful = std::max(need, (m + 255) / 256);
-    wgs = std::min(wgs, std::max(need, useful));
-    if (wgs > kMaxCand || wgs > s.num_cus) return -1;
+    // Rows per work-group: up to 2*threads (the register-resident variants),
+    // 4*threads only when even kPanelMaxWgs groups would not cover m that way.
+    const int t = panel_threads();
+    int need = (m + 2 * t - 1) / (2 * t);
+    if (need > kPanelMaxWgs) need = (m + panel_max_rows_per_wg() - 1) / panel_max_rows_per_wg();
+    // no more groups than rows / threads: fewer, fuller groups make cheaper barriers
+    const int useful = std::max(need, (m + t - 1) / t);
+    const int wgs = std::min(std::max(need, std::max(1, panel_cus)), useful);
+    if (wgs > kPanelMaxWgs || wgs > s.num_cus) return -1;
     return wgs;
 }
 
@@ -188,22 +191,6 @@ const std::vector<PlanTask>* get_plan(DeviceState* s, int n, int b, int depth) {
 // ---------------------------------------------------------------- executor
 struct HalfNone {};
 
-template <typename T> struct CandPtrs {
-    T* val; int* idx; T* rows; T* diag;
-};
-
-template <typename T>
-CandPtrs<T> cand_ptrs(DeviceState* s) {
-    char* base = reinterpret_cast<char*>(s->cand.ptr);
-    CandPtrs<T> c;
-    c.val = reinterpret_cast<T*>(base);
-    c.idx = reinterpret_cast<int*>(base + 2 * kMaxCand * sizeof(double));
-    c.rows = reinterpret_cast<T*>(base + 2 * kMaxCand * sizeof(double) + 2 * kMaxCand * sizeof(int));
-    c.diag = reinterpret_cast<T*>(base + 2 * kMaxCand * sizeof(double) + 2 * kMaxCand * sizeof(int) +
-                                  2 * kMaxCand * kNB * sizeof(double));
-    return c;
-}
-
 template <typename T>
 int run_panel(DeviceState* s, T* A, long long lda, int n, int j0, int w, int* ipiv, int* info, int* moves,
               int wgs_req, hipStream_t st) {
@@ -222,9 +209,17 @@ int run_panel(DeviceState* s, T* A, long long lda, int n, int j0, int w, int* ip
     pa.sync = s->sync + 2 * s->sync_slot;   // [counter, error]
     pa.sync_next = s->sync + 2 * (1 - s->sync_slot);
     s->sync_slot = 1 - s->sync_slot;
-    CandPtrs<T> c = cand_ptrs<T>(s);
-    pa.cand_val = c.val; pa.cand_idx = c.idx; pa.cand_rows = c.rows; pa.diag_rows = c.diag;
+    pa.xch = reinterpret_cast<unsigned long long*>(s->cand.ptr);
+    // tags: 22 bits of launch number, 10 bits of column (w <= 512); tag 0 is never used
+    s->panel_launches = (s->panel_launches + 1) & 0x3fffff;
+    if (s->panel_launches == 0) {
+        // numbering wrapped: clear words that could still carry a reused tag
+        s->panel_launches = 1;
+        if (launch_fill_zero(s->cand.ptr, s->cand.bytes, st) != 0) return LU_ERR_HIP;
+    }
+    pa.tag_base = (unsigned)s->panel_launches << 10;
     pa.spin_limit = s->spin_limit;
+    pa.occupancy = s->panel_occupancy;
     int wgs = panel_wgs_for(*s, m, wgs_req);
     if (wgs < 0) return LU_ERR_UNSUPPORTED;
     return launch_panel<T>(pa, wgs, st) == 0 ? 0 : LU_ERR_HIP;

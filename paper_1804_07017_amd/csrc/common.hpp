@@ -29,6 +29,18 @@ __device__ __forceinline__ void wave_argmax(T& v, int& i) {
     }
 }
 
+// Device-coherent exchange words.  Agent-scope relaxed atomic loads and stores
+// go to the device coherence point and bypass the non-coherent per-CU / per-XCD
+// caches, so data published this way needs no cache write-back or invalidate.
+template <typename T>
+__device__ __forceinline__ void xstore(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T xload(const T* p) {
+    return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Device-wide barrier among the gridDim.x work-groups of one launch.  All of
 // them must be resident at once (the host sizes the grid for that).  The
 // counter starts at 0 for the launch; barrier number `epoch` (1-based) waits
@@ -36,31 +48,40 @@ __device__ __forceinline__ void wave_argmax(T& v, int& i) {
 // `limit` ticks of the constant-rate wall clock, or when another work-group
 // has already failed, the error word is set and true is returned so that the
 // caller exits instead of hanging.
+//
+// full = true : every wave makes its ordinary global writes visible
+//               device-wide before arriving and re-reads device-wide data
+//               after leaving (release / acquire fences at agent scope).
+// full = false: only data exchanged through xstore/xload is ordered: each
+//               wave waits for its own outstanding memory operations to
+//               complete before the work-group arrives, and the counter is a
+//               relaxed device-scope atomic.  No cache maintenance.
 __device__ __forceinline__ bool grid_barrier(unsigned* counter, unsigned* err, unsigned epoch,
-                                             long long limit) {
+                                             long long limit, bool full = true) {
     __shared__ int s_fail;
-    // every wave makes its own global writes visible device-wide before the
-    // work-group arrives, and re-reads device-wide data after it leaves
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (full) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    else __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && gridDim.x > 1) {   // a single work-group needs only its own barrier
         const unsigned target = epoch * gridDim.x;
-        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (full) __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        else __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         int fail = 0;
         const long long t0 = wall_clock64();
-        while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) { fail = 1; break; }
             if (wall_clock64() - t0 > limit) {
                 __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 fail = 1;
                 break;
             }
-            __builtin_amdgcn_s_sleep(1);
         }
         s_fail = fail;
+    } else if (threadIdx.x == 0) {
+        s_fail = 0;
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (full) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return s_fail != 0;
 }
 

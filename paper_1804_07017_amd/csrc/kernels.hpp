@@ -11,6 +11,11 @@ namespace lu {
 constexpr int kMovesMaxW = 512;
 constexpr int kMovesExtra = 2 + 2 * kMovesMaxW;
 constexpr int kMovesLen = 2 + 4 * kMovesMaxW;
+// The panel kernel runs at most this many cooperating work-groups (rows per
+// work-group <= 1024, so panels up to 65536 rows).
+constexpr int kPanelMaxWgs = 64;
+// size of the panel kernel's tagged exchange area, in 64-bit words (both parities)
+constexpr int kPanelXchWords = 2 * (kPanelMaxWgs * (1 + 2 + 2 * 16 * 2) + 2 * 16 * 2);
 
 template <typename T>
 struct PanelArgs {
@@ -25,16 +30,16 @@ struct PanelArgs {
     int* moves;           // optional composed interchanges (kMovesLen ints)
     unsigned* sync;       // [0] barrier counter (0 at launch), [1] error word
     unsigned* sync_next;  // counter of the alternate slot, zeroed by this launch
-    T* cand_val;          // [2][P]
-    int* cand_idx;        // [2][P]
-    T* cand_rows;         // [2][P][16]
-    T* diag_rows;         // [2][16]
+    unsigned long long* xch;   // tagged exchange area (kPanelXchWords words)
+    unsigned tag_base;    // unique per launch: (launch number << 10); step d uses tag_base + d
     long long spin_limit; // barrier wait bound, wall-clock ticks
+    int occupancy;        // register budget variant: 1 = whole register file, 2 = half
 };
 
 template <typename T>
 int launch_panel(const PanelArgs<T>& args, int wgs, hipStream_t stream);
 int panel_max_rows_per_wg();
+int panel_threads();
 
 template <typename T, typename H>
 struct SwapTrsmArgs {

@@ -18,25 +18,34 @@ namespace {
 constexpr int kRB = 64;          // rows per triangular block
 constexpr int kThreads = 256;    // 4 column groups x 64 rows
 
+// Wait until a block's ready flag shows `epoch` (relaxed device-scope polls;
+// the block's x values are read with device-coherent loads afterwards).
 __device__ __forceinline__ bool wait_flag(const int* flag, int epoch, unsigned* err, long long limit) {
     __shared__ int s_fail;
     if (threadIdx.x == 0) {
         int fail = 0;
         const long long t0 = wall_clock64();
-        while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) { fail = 1; break; }
+        while (xload(flag) != epoch) {
+            if (xload(err) != 0u) { fail = 1; break; }
             if (wall_clock64() - t0 > limit) {
-                __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                xstore(err, 1u);
                 fail = 1;
                 break;
             }
-            __builtin_amdgcn_s_sleep(1);
         }
         s_fail = fail;
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return s_fail != 0;
+}
+
+// Publish x(r) and then its flag: the x stores complete before the flag store.
+template <typename T>
+__device__ __forceinline__ void publish(T* x, int row, T y, bool valid, int* flag, int epoch) {
+    if (valid) xstore(&x[row], y);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) xstore(flag, epoch);
 }
 
 template <typename T>
@@ -44,32 +53,33 @@ __global__ __launch_bounds__(kThreads) void trsv_lower_unit_kernel(const T* __re
                                                                     T* __restrict__ x, int* flags, int epoch,
                                                                     unsigned* err, long long limit) {
     __shared__ T part[4][kRB];
+    __shared__ T Ld[kRB][kRB + 1];
     const int r = blockIdx.x;
     const int tid = threadIdx.x, i = tid % kRB, g = tid / kRB;
     const int row = r * kRB + i;
+    const int nb = min(kRB, n - r * kRB);
+    // the diagonal block does not depend on other blocks: stage it first
+    for (int s = g; s < kRB; s += 4) Ld[s][i] = (row < n && s < nb) ? LU[row + (long long)(r * kRB + s) * lda] : T(0);
     T acc = T(0);
     for (int cb = 0; cb < r; ++cb) {
         if (wait_flag(&flags[cb], epoch, err, limit)) return;
         if (row < n) {
             const int j0 = cb * kRB;
 #pragma unroll 4
-            for (int jj = g; jj < kRB; jj += 4) acc += LU[row + (long long)(j0 + jj) * lda] * x[j0 + jj];
+            for (int jj = g; jj < kRB; jj += 4) acc += LU[row + (long long)(j0 + jj) * lda] * xload(&x[j0 + jj]);
         }
     }
     part[g][i] = acc;
     __syncthreads();
+    T y = T(0);
     if (tid < kRB) {
-        T y = (row < n) ? x[row] - ((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) : T(0);
-        const int nb = min(kRB, n - r * kRB);
+        y = (row < n) ? x[row] - ((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) : T(0);
         for (int s = 0; s < nb; ++s) {
             const T xs = __shfl(y, s, kWave);
-            if (i > s && row < n) y -= LU[row + (long long)(r * kRB + s) * lda] * xs;
+            if (i > s) y -= Ld[s][i] * xs;
         }
-        if (row < n) x[row] = y;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     }
-    __syncthreads();
-    if (tid == 0) __hip_atomic_store(&flags[r], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    publish(x, row, y, tid < kRB && row < n, &flags[r], epoch);
 }
 
 template <typename T>
@@ -77,10 +87,13 @@ __global__ __launch_bounds__(kThreads) void trsv_upper_kernel(const T* __restric
                                                                T* __restrict__ x, int* flags, int epoch,
                                                                unsigned* err, long long limit) {
     __shared__ T part[4][kRB];
+    __shared__ T Ud[kRB][kRB + 1];
     const int nblk = (n + kRB - 1) / kRB;
     const int r = nblk - 1 - (int)blockIdx.x;         // bottom block first
     const int tid = threadIdx.x, i = tid % kRB, g = tid / kRB;
     const int row = r * kRB + i;
+    const int nb = min(kRB, n - r * kRB);
+    for (int s = g; s < kRB; s += 4) Ud[s][i] = (row < n && s < nb) ? LU[row + (long long)(r * kRB + s) * lda] : T(0);
     T acc = T(0);
     for (int cb = nblk - 1; cb > r; --cb) {
         if (wait_flag(&flags[cb], epoch, err, limit)) return;
@@ -88,25 +101,21 @@ __global__ __launch_bounds__(kThreads) void trsv_upper_kernel(const T* __restric
             const int j0 = cb * kRB;
             const int nj = min(kRB, n - j0);
 #pragma unroll 4
-            for (int jj = g; jj < nj; jj += 4) acc += LU[row + (long long)(j0 + jj) * lda] * x[j0 + jj];
+            for (int jj = g; jj < nj; jj += 4) acc += LU[row + (long long)(j0 + jj) * lda] * xload(&x[j0 + jj]);
         }
     }
     part[g][i] = acc;
     __syncthreads();
+    T y = T(0);
     if (tid < kRB) {
-        T y = (row < n) ? x[row] - ((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) : T(0);
-        const int nb = min(kRB, n - r * kRB);
+        y = (row < n) ? x[row] - ((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) : T(0);
         for (int s = nb - 1; s >= 0; --s) {
-            T xs = T(0);
-            if (i == s) { y = y / LU[row + (long long)row * lda]; }
-            xs = __shfl(y, s, kWave);
-            if (i < s) y -= LU[row + (long long)(r * kRB + s) * lda] * xs;
+            if (i == s) y = y / Ud[s][i];
+            const T xs = __shfl(y, s, kWave);
+            if (i < s) y -= Ud[s][i] * xs;
         }
-        if (row < n) x[row] = y;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     }
-    __syncthreads();
-    if (tid == 0) __hip_atomic_store(&flags[r], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    publish(x, row, y, tid < kRB && row < n, &flags[r], epoch);
 }
 
 // P x for each right-hand side: chunk c's interchanges, chunks in order.

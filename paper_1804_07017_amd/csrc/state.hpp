@@ -28,6 +28,7 @@ struct DeviceState {
     int dev = -1;
     int num_cus = 0;
     long long spin_limit = 0;          // ~2 s of the device wall clock
+    int panel_occupancy = 1;           // panel kernel register budget variant (LU_PANEL_OCC)
     hipStream_t panel_stream = nullptr;
     std::vector<hipEvent_t> events;    // ring used for cross-stream dependencies
     int ev_next = 0;
@@ -35,6 +36,7 @@ struct DeviceState {
     // panel barrier words: 2 slots x (counter, error); slot alternates per launch
     unsigned* sync = nullptr;
     int sync_slot = 0;
+    unsigned panel_launches = 0;       // numbers the panel launches (exchange tags)
     Buffer cand;                       // candidate exchange area of the panel kernel
     Buffer moves;                      // per-panel composed interchanges
     int* info = nullptr;               // library INFO word

@@ -46,50 +46,111 @@ __global__ __launch_bounds__(kThreads) void swap_trsm_kernel(SwapTrsmArgs<T, H> 
     const int nc = min(BN, a.c1 - c_base);
     const long long lda = a.lda;
     T* __restrict__ Atop = a.A + a.r0;                  // row r0 of column 0
-    const int* __restrict__ mv = a.moves;
-    const int ntop = mv[0], nex = mv[1];
+    __shared__ int mv[2 * 2 * kMovesMaxW];   // (dst, src): top moves, then extra moves
+    const int ntop = a.moves[0], nex = a.moves[1];
+    for (int s = tid; s < ntop; s += kThreads) { mv[2 * s] = a.moves[2 + 2 * s]; mv[2 * s + 1] = a.moves[3 + 2 * s]; }
+    for (int s = tid; s < nex; s += kThreads) {
+        mv[2 * (ntop + s)] = a.moves[kMovesExtra + 2 * s];
+        mv[2 * (ntop + s) + 1] = a.moves[kMovesExtra + 1 + 2 * s];
+    }
 
-    // 1. gather (reads only)
-    for (int e = tid; e < w * BN; e += kThreads) {
-        const int t = e % w, c = e / w;
-        X[t * ldx + c] = (c < nc) ? Atop[t + (long long)(c_base + c) * lda] : T(0);
+    // 1. gather (reads only), batched so that many loads are in flight
+    constexpr int kBatch = 8;
+    for (int e0 = tid; e0 < w * BN; e0 += kThreads * kBatch) {
+        T v[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int e = e0 + u * kThreads;
+            const int t = e % w, c = e / w;
+            v[u] = (e < w * BN && c < nc) ? Atop[t + (long long)(c_base + c) * lda] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int e = e0 + u * kThreads;
+            if (e < w * BN) X[(e % w) * ldx + e / w] = v[u];
+        }
     }
     __syncthreads();
-    for (int e = tid; e < ntop * BN; e += kThreads) {
-        const int s = e / BN, c = e % BN;
-        if (c < nc) X[mv[2 + 2 * s] * ldx + c] = Atop[mv[3 + 2 * s] + (long long)(c_base + c) * lda];
-    }
-    for (int e = tid; e < nex * BN; e += kThreads) {
-        const int s = e / BN, c = e % BN;
-        if (c < nc) V[s * BN + c] = Atop[mv[kMovesExtra + 1 + 2 * s] + (long long)(c_base + c) * lda];
+    const int cnt = ntop + nex;
+    for (int e0 = tid; e0 < cnt * BN; e0 += kThreads * kBatch) {
+        T v[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int e = e0 + u * kThreads;
+            const int s = e / BN, c = e % BN;
+            v[u] = (e < cnt * BN && c < nc) ? Atop[mv[2 * s + 1] + (long long)(c_base + c) * lda] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int e = e0 + u * kThreads;
+            if (e < cnt * BN) {
+                const int s = e / BN, c = e % BN;
+                if (s < ntop) X[mv[2 * s] * ldx + c] = v[u];
+                else V[(s - ntop) * BN + c] = v[u];
+            }
+        }
     }
     __syncthreads();
     // scatter of the extra rows, after every read of these columns
     for (int e = tid; e < nex * BN; e += kThreads) {
         const int s = e / BN, c = e % BN;
-        if (c < nc) Atop[mv[kMovesExtra + 2 * s] + (long long)(c_base + c) * lda] = V[s * BN + c];
+        if (c < nc) Atop[mv[2 * (ntop + s)] + (long long)(c_base + c) * lda] = V[s * BN + c];
     }
     __syncthreads();
 
-    // 2. forward substitution with unit-lower L11, staged by KC-column chunks into V
-    const int KC = BN;
+    // 2. forward substitution with unit-lower L11 in blocks of KB rows:
+    //    (a) the KB x KB diagonal block, one thread per column;
+    //    (b) the rows below, X[i] -= L[i, blk] X[blk], all threads.
+    //    L11's block columns are staged into V (w x BN values >= (w-k0) x KB);
+    //    the next block's columns are loaded into registers while the current
+    //    block is being solved, so their latency is hidden.
+    constexpr int kPre = 16;                      // staged values per thread per block
+    // KB <= BN (V capacity) and w*KB <= kPre*256 (register prefetch capacity)
+    const int KB = min(min(BN, 16), (kPre * kThreads) / w);
     const T* __restrict__ L = a.A + a.r0 + (long long)a.r0 * lda;   // L11 at (r0, r0)
-    for (int k0 = 0; k0 < w; k0 += KC) {
-        const int kc = min(KC, w - k0);
-        for (int e = tid; e < w * kc; e += kThreads) {
-            const int i = e % w, kk = e / w;
-            V[i * KC + kk] = (i > k0 + kk) ? L[i + (long long)(k0 + kk) * lda] : T(0);
+    T pre[kPre];
+    auto fetch = [&](int k0) {
+        const int rows = w - k0, kb = min(KB, w - k0);
+#pragma unroll
+        for (int u = 0; u < kPre; ++u) {
+            const int e = tid + u * kThreads;
+            const int i = e % rows, s = e / rows;
+            const bool ok = e < rows * kb;
+            pre[u] = L[(k0 + (ok ? i : 0)) + (long long)(k0 + (ok ? s : 0)) * lda];
+        }
+    };
+    auto stage = [&](int k0) {
+        const int rows = w - k0, kb = min(KB, w - k0);
+#pragma unroll
+        for (int u = 0; u < kPre; ++u) {
+            const int e = tid + u * kThreads;
+            if (e < rows * kb) V[(e % rows) * KB + e / rows] = pre[u];
+        }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < w; k0 += KB) {
+        const int kb = min(KB, w - k0);
+        const int rows = w - k0;
+        stage(k0);
+        __syncthreads();
+        if (k0 + KB < w) fetch(k0 + KB);
+        if (tid < BN) {
+            const int c = tid;
+            for (int s = 0; s < kb; ++s) {
+                const T xs = X[(k0 + s) * ldx + c];
+                for (int r = s + 1; r < kb; ++r) X[(k0 + r) * ldx + c] -= V[r * KB + s] * xs;
+            }
         }
         __syncthreads();
-        for (int kk = 0; kk < kc; ++kk) {
-            const int k = k0 + kk;
-            const int rows = w - k - 1;
-            for (int e = tid; e < rows * BN; e += kThreads) {
-                const int i = k + 1 + e / BN, c = e % BN;
-                X[i * ldx + c] = X[i * ldx + c] - V[i * KC + kk] * X[k * ldx + c];
-            }
-            __syncthreads();
+        const int below = rows - kb;
+        for (int e = tid; e < below * BN; e += kThreads) {
+            const int ii = kb + e / BN, c = e % BN;
+            T acc = X[(k0 + ii) * ldx + c];
+#pragma unroll 4
+            for (int s = 0; s < kb; ++s) acc -= V[ii * KB + s] * X[(k0 + s) * ldx + c];
+            X[(k0 + ii) * ldx + c] = acc;
         }
+        __syncthreads();
     }
     // 3. U12 back to the matrix (and the scaled half copy)
     for (int e = tid; e < w * BN; e += kThreads) {
