@@ -27,23 +27,21 @@ FP64_PEAK_TFLOPS = 78.6
 
 
 def cpu_baseline(budget_s=20.0):
-    """Time the CPU oracle on a bounded sample of the same workload."""
-    import numpy as np
+    """Time the CPU oracle on a bounded sample of the same workload: one
+    factorization of a smaller uniform[-1,1) matrix, sized by cubic
+    extrapolation from shorter runs to take about budget_s."""
     import oracle
     import synth
     cores = min(16, len(os.sched_getaffinity(0)))
-    # calibrate on a small case, then pick n for ~budget_s of work (cubic scaling)
-    n0 = 768
-    A = synth.uniform(n0, seed=7)
-    t0 = time.perf_counter()
-    oracle.getrf(A, nthreads=cores)
-    t_small = time.perf_counter() - t0
-    n = int(n0 * (budget_s / max(t_small, 1e-3)) ** (1 / 3))
-    n = max(n0, min(n, 8192)) // 64 * 64
-    A = synth.uniform(n, seed=1)
-    t0 = time.perf_counter()
-    oracle.getrf(A, nthreads=cores)
-    t = time.perf_counter() - t0
+    n, t = 1024, 0.0
+    for _ in range(4):
+        A = synth.uniform(n, seed=1)
+        t0 = time.perf_counter()
+        oracle.getrf(A, nthreads=cores)
+        t = time.perf_counter() - t0
+        if t >= 0.4 * budget_s or n >= 16384:
+            break
+        n = min(16384, max(n + 256, int(n * (budget_s / max(t, 1e-3)) ** (1 / 3)))) // 256 * 256
     return {"value": round((2.0 / 3.0) * n ** 3 / t / 1e9, 3), "unit": "GFLOP/s", "cores": cores,
             "kind": "oracle",
             "sample": "one FP64 partial-pivoting LU of a uniform[-1,1) %dx%d matrix (%.1f s)" % (n, n, t)}

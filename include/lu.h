@@ -140,8 +140,10 @@ int lu_solve_ir(int n, int nrhs, const double* A, int lda, const double* B, int 
  * GPU kernels. */
 
 /* Load weights written by lu_selector_save / the training script (host path).
- * Returns 0, or <0 if the file is missing or corrupt; the fixed default then
- * stays active. */
+ * Returns 0, or <0 if the file is missing or corrupt, in which case whatever
+ * was active before (weights, or the fixed default) stays active.
+ * path == NULL drops the active weights: the fixed default is used from then
+ * on, also for the weights file next to the library (returns 0). */
 int lu_selector_load(const char* path);
 
 /* Predict the schedule for (n, prec) into *out (host).  Returns 0, or 1 when

@@ -202,7 +202,8 @@ def lu_solve_ir(A, B, X, prec=LU_MIXED_FP16, max_iter=10, stream=None):
 
 
 def lu_selector_load(path):
-    return load().lu_selector_load(str(path).encode())
+    """path None: drop the active weights (the fixed default is used)."""
+    return load().lu_selector_load(None if path is None else str(path).encode())
 
 
 def lu_selector_save(path):

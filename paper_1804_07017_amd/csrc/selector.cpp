@@ -157,8 +157,13 @@ using lu::g;
 extern "C" {
 
 int lu_selector_load(const char* path) {
-    if (!path) return -1;
     g.tried_default = true;
+    if (!path) {
+        g.loaded = false;
+        g.cache.clear();
+        g.adam_t = 0;
+        return 0;
+    }
     return lu::load_file(path);
 }
 

@@ -177,3 +177,74 @@ def test_c2_8192_lookahead_and_solve(gpu):
         torch.cuda.synchronize()
         x = gpu.to_host(db)[:, 0]
         assert oracle.r_hpl(A, x, b[:, 0]) <= 16.0
+
+
+def _device_residual(gpu, dA0, dLU, ipiv):
+    """||P A - L U||_F / (||A||_F n eps), computed with torch's FP64 GEMM in
+    column slabs so that only one n x slab product is alive at a time."""
+    import torch
+    n = dA0.shape[0]
+    perm = torch.tensor(oracle.perm_from_ipiv(ipiv), device="cuda")
+    L = torch.tril(dLU, -1)
+    L.diagonal().fill_(1.0)
+    acc = 0.0
+    slab = 4096
+    for c0 in range(0, n, slab):
+        c1 = min(n, c0 + slab)
+        U = torch.triu(dLU[:, c0:c1], diagonal=-c0)[:c1, :]      # rows < c1 of U's columns c0..c1
+        R = dA0[perm, c0:c1] - L[:, :c1] @ U
+        acc += float((R * R).sum().item())
+        del U, R
+    del L
+    return acc ** 0.5 / (torch.linalg.norm(dA0).item() * n * 2.0 ** -53)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("b,depth,cus", [(256, 1, 16), (512, 2, 8)])
+def test_c3_32768_uniform(gpu, b, depth, cus):
+    """Full-size FP64 look-ahead LU: scaled residual with a library GEMM, the
+    pivots are a legal permutation, every multiplier is bounded by 1, and the
+    first panel's pivots equal the oracle's (a plain column search over A)."""
+    import torch
+    n = 32768
+    A = synth.uniform(n, seed=1)
+    dA0 = gpu.to_device(A)
+    a00 = A[:, 0].copy()
+    del A
+    dA = dA0.clone()
+    ipiv = torch.zeros(n, dtype=torch.int32, device="cuda")
+    assert gpu.lu_factor_ex(dA, ipiv, sched=(b, depth, cus)) == 0
+    torch.cuda.synchronize()
+    assert gpu.lu_factor_info() == (0, 0)
+    ip = ipiv.cpu().numpy()
+    assert (ip >= np.arange(n)).all() and (ip < n).all()
+    assert ip[0] == int(np.argmax(np.abs(a00)))
+    assert torch.tril(dA, -1).abs().max().item() <= 1.0
+    rf = _device_residual(gpu, dA0, dA, ip)
+    assert rf <= 16.0, rf
+
+
+@pytest.mark.timeout(900)
+def test_c3_32768_planted_factors(gpu):
+    """A = P L U with L scaled to a = 0.1 sqrt(1024/n) (||L^-1|| as at n=1024):
+    the pivots and both factors are recovered."""
+    import torch
+    n = 32768
+    a_l = 0.1 * (1024.0 / n) ** 0.5
+
+    def mm(X, Y):
+        return (torch.from_numpy(X).cuda() @ torch.from_numpy(Y).cuda()).cpu().numpy()
+
+    A, L, U, perm = synth.planted(n, seed=4, a_l=a_l, matmul=mm)
+    dA = gpu.to_device(A)
+    del A
+    ipiv = torch.zeros(n, dtype=torch.int32, device="cuda")
+    assert gpu.lu_factor_ex(dA, ipiv, sched=(256, 1, 16)) == 0
+    torch.cuda.synchronize()
+    assert np.array_equal(ipiv.cpu().numpy(), pins.planted_ipiv(perm))
+    dL = torch.from_numpy(L).cuda()
+    errL = (torch.tril(dA, -1) - torch.tril(dL, -1)).abs().max().item()
+    del dL
+    dU = torch.from_numpy(U).cuda()
+    errU = (torch.triu(dA) - dU).abs().max().item() / dU.abs().max().item()
+    assert errL <= 1e-12 and errU <= 1e-12, (errL, errU)
