@@ -13,9 +13,11 @@
  * A schedule places these tasks in a program order that is a valid
  * sequential order of the algorithm (Listing 3 for depth 0, Listing 5 of
  * Sec. 4 for depth 1, two panels ahead for depth 2) and assigns each to one
- * of two streams: 0 = the update stream (the caller's stream), 1 = the panel
- * stream.  Each task lists the earlier tasks of the OTHER stream it must wait
- * for; these are derived mechanically from the column ranges and pivot
+ * of LU_PLAN_STREAMS streams: 0 = the update stream (the caller's stream),
+ * 1 = the panel stream, 2 = the stream of the left interchanges (depth >= 1;
+ * depth 0 keeps every task on stream 0).  Each task lists the earlier tasks
+ * of OTHER streams it must wait for (at most one per stream); these are
+ * derived mechanically from the column ranges and pivot
  * blocks each task reads and writes, so concurrently runnable tasks touch
  * disjoint data and every execution order the streams allow gives the
  * result of the program order.
@@ -31,15 +33,16 @@ extern "C" {
 #define LU_TASK_UPDATE 1
 #define LU_TASK_LSWAP  2
 
-#define LU_PLAN_MAX_WAIT 2
+#define LU_PLAN_STREAMS  3
+#define LU_PLAN_MAX_WAIT 2   /* = LU_PLAN_STREAMS - 1 */
 
 typedef struct {
     int kind;                   /* LU_TASK_*                                          */
     int step;                   /* k (PANEL: the panel index j)                       */
     int col_begin, col_end;     /* columns written, [col_begin, col_end)              */
-    int stream;                 /* 0 = update stream, 1 = panel stream                */
+    int stream;                 /* 0 update, 1 panel, 2 left interchanges             */
     int nwait;                  /* cross-stream waits                                 */
-    int wait[LU_PLAN_MAX_WAIT]; /* indices of earlier tasks (other stream) to wait on */
+    int wait[LU_PLAN_MAX_WAIT]; /* indices of earlier tasks (other streams) to wait on */
     int record;                 /* 1 if a later task waits on this one                */
 } lu_plan_task_t;
 

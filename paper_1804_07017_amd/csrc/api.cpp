@@ -99,7 +99,8 @@ DeviceState* device_state(int* err) {
         long long v = std::atoll(e);
         if (v > 0) s->spin_limit = v;                    // debug knob: tiny bound forces the timeout path
     }
-    if (hipStreamCreateWithFlags(&s->panel_stream, hipStreamNonBlocking) != hipSuccess) {
+    if (hipStreamCreateWithFlags(&s->panel_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&s->swap_stream, hipStreamNonBlocking) != hipSuccess) {
         *err = LU_ERR_HIP; delete s; return nullptr;
     }
     s->events.resize(kEventRing);
@@ -123,9 +124,10 @@ void release_all() {
         hipDeviceSynchronize();
         for (auto& e : s->events) hipEventDestroy(e);
         if (s->panel_stream) hipStreamDestroy(s->panel_stream);
+        if (s->swap_stream) hipStreamDestroy(s->swap_stream);
         if (s->sync) hipFree(s->sync);
         if (s->info) hipFree(s->info);
-        Buffer* bufs[] = {&s->cand, &s->moves, &s->lh, &s->uh, &s->rs, &s->cs, &s->solve_moves, &s->flags,
+        Buffer* bufs[] = {&s->cand, &s->moves, &s->linv, &s->lh, &s->uh, &s->rs, &s->cs, &s->solve_moves, &s->flags,
                           &s->partial, &s->ir_r, &s->ir_x32, &s->ir_a32, &s->ir_a64, &s->ir_norms, &s->ir_ipiv,
                           &s->ir_b};
         for (Buffer* b : bufs) release(*b);
@@ -235,6 +237,10 @@ int execute(DeviceState* s, int n, T* A, long long lda, int* ipiv, int* info, co
     int rc;
     if ((rc = ensure(s->moves, (size_t)N * kMovesLen * sizeof(int)))) return rc;
     int* moves = reinterpret_cast<int*>(s->moves.ptr);
+    // inverses of each panel's 16x16 diagonal L blocks (one slot per panel)
+    constexpr size_t kLinvPer = (size_t)(kMovesMaxW / 16) * 256;
+    if ((rc = ensure(s->linv, (size_t)N * kLinvPer * sizeof(T)))) return rc;
+    T* linv = reinterpret_cast<T*>(s->linv.ptr);
     // mixed precision operand copies
     H* Lh = nullptr; H* Uh = nullptr; float* rs = nullptr; float* cs = nullptr;
     long long ldh = 0, lduh = 0;
@@ -250,11 +256,12 @@ int execute(DeviceState* s, int n, T* A, long long lda, int* ipiv, int* info, co
         rs = reinterpret_cast<float*>(s->rs.ptr);
         cs = reinterpret_cast<float*>(s->cs.ptr);
     }
-    hipStream_t streams[2] = {stream, s->panel_stream};
-    // entry join: the panel stream starts after everything already on `stream`
+    hipStream_t streams[kPlanStreams] = {stream, s->panel_stream, s->swap_stream};
+    // entry join: the library streams start after everything already on `stream`
     hipEvent_t ev0 = s->events[s->ev_next]; s->ev_next = (s->ev_next + 1) % kEventRing;
     LU_HIP(hipEventRecord(ev0, stream));
     LU_HIP(hipStreamWaitEvent(s->panel_stream, ev0, 0));
+    LU_HIP(hipStreamWaitEvent(s->swap_stream, ev0, 0));
     std::vector<int> ev_of(plan->size(), -1);
     for (size_t ti = 0; ti < plan->size(); ++ti) {
         const PlanTask& t = (*plan)[ti];
@@ -270,6 +277,7 @@ int execute(DeviceState* s, int n, T* A, long long lda, int* ipiv, int* info, co
         int* mv = moves + (size_t)k * kMovesLen;
         if (t.kind == kTaskPanel) {
             if ((rc = run_panel<T>(s, A, lda, n, kb, wk, ipiv, info, mv, sch.panel_cus, st))) return rc;
+            if (launch_diag_inv<T>(A, lda, kb, wk, linv + (size_t)k * kLinvPer, st)) return LU_ERR_HIP;
             if (mixed && n - kb - wk > 0) {
                 if (launch_l21_half<H>(reinterpret_cast<const float*>(A) + (kb + wk) + (long long)kb * lda, lda,
                                        n - kb - wk, wk, Lh + (long long)(kb + wk) * ldh + kb, ldh,
@@ -279,7 +287,7 @@ int execute(DeviceState* s, int n, T* A, long long lda, int* ipiv, int* info, co
         } else if (t.kind == kTaskUpdate) {
             SwapTrsmArgs<T, H> sa;
             sa.A = A; sa.lda = lda; sa.r0 = kb; sa.w = wk; sa.moves = mv;
-            sa.c0 = t.col_begin; sa.c1 = t.col_end; sa.bn = 0;
+            sa.c0 = t.col_begin; sa.c1 = t.col_end; sa.linv = linv + (size_t)k * kLinvPer;
             sa.uh = mixed ? Uh + kb : nullptr;
             sa.lduh = lduh;
             sa.cs = mixed ? cs + (size_t)k * n : nullptr;
@@ -314,9 +322,11 @@ int execute(DeviceState* s, int n, T* A, long long lda, int* ipiv, int* info, co
         }
     }
     // exit join
-    hipEvent_t ev1 = s->events[s->ev_next]; s->ev_next = (s->ev_next + 1) % kEventRing;
-    LU_HIP(hipEventRecord(ev1, s->panel_stream));
-    LU_HIP(hipStreamWaitEvent(stream, ev1, 0));
+    for (int u = 1; u < kPlanStreams; ++u) {
+        hipEvent_t ev1 = s->events[s->ev_next]; s->ev_next = (s->ev_next + 1) % kEventRing;
+        LU_HIP(hipEventRecord(ev1, streams[u]));
+        LU_HIP(hipStreamWaitEvent(stream, ev1, 0));
+    }
     return 0;
 }
 
@@ -461,16 +471,21 @@ int lu_k_update(lu_precision_t prec, int m, int w, int ncols, const void* L, int
     if (off_bytes <= 0 || off_bytes % (esz * (long long)ldc) != 0) return LU_ERR_UNSUPPORTED;
     const int c0 = (int)(off_bytes / (esz * (long long)ldc));
     if (c0 < w) return LU_ERR_UNSUPPORTED;
+    if ((rc = lu::ensure(s->linv, (size_t)(lu::kMovesMaxW / 16) * 256 * esz))) return rc;
     if (prec == LU_FP64) {
         double* A = const_cast<double*>(reinterpret_cast<const double*>(L));
-        lu::SwapTrsmArgs<double, _Float16> sa{A, ldl, 0, w, mv, c0, c0 + ncols, 0, nullptr, 0, nullptr};
+        double* linv = reinterpret_cast<double*>(s->linv.ptr);
+        if (lu::launch_diag_inv<double>(A, ldl, 0, w, linv, stream)) return LU_ERR_HIP;
+        lu::SwapTrsmArgs<double, _Float16> sa{A, ldl, 0, w, mv, c0, c0 + ncols, linv, nullptr, 0, nullptr};
         if (lu::launch_swap_trsm<double, _Float16>(sa, stream)) return LU_ERR_HIP;
         if (m > w && lu::launch_gemm<double>(m - w, ncols, w, A + w, ldl, A + (long long)c0 * ldl, ldl,
                                              A + w + (long long)c0 * ldl, ldl, stream))
             return LU_ERR_HIP;
     } else {
         float* A = const_cast<float*>(reinterpret_cast<const float*>(L));
-        lu::SwapTrsmArgs<float, _Float16> sa{A, ldl, 0, w, mv, c0, c0 + ncols, 0, nullptr, 0, nullptr};
+        float* linv = reinterpret_cast<float*>(s->linv.ptr);
+        if (lu::launch_diag_inv<float>(A, ldl, 0, w, linv, stream)) return LU_ERR_HIP;
+        lu::SwapTrsmArgs<float, _Float16> sa{A, ldl, 0, w, mv, c0, c0 + ncols, linv, nullptr, 0, nullptr};
         if (lu::launch_swap_trsm<float, _Float16>(sa, stream)) return LU_ERR_HIP;
         if (m > w && lu::launch_gemm<float>(m - w, ncols, w, A + w, ldl, A + (long long)c0 * ldl, ldl,
                                             A + w + (long long)c0 * ldl, ldl, stream))

@@ -19,6 +19,49 @@ __device__ __forceinline__ void argmax_merge(T& v, int& i, T ov, int oi) {
     if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
 }
 
+// Cross-lane moves by DPP (no LDS traffic): CTRL is a gfx9 dpp_ctrl code.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int x) { return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false); }
+template <int CTRL>
+__device__ __forceinline__ float dpp_t(float x) { return __int_as_float(dpp_i32<CTRL>(__float_as_int(x))); }
+template <int CTRL>
+__device__ __forceinline__ double dpp_t(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = dpp_i32<CTRL>((int)b), hi = dpp_i32<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ int lane_i32(int x, int l) { return __builtin_amdgcn_readlane(x, l); }
+__device__ __forceinline__ float lane_t(float x, int l) { return __int_as_float(lane_i32(__float_as_int(x), l)); }
+__device__ __forceinline__ double lane_t(double x, int l) {
+    const long long b = __double_as_longlong(x);
+    const int lo = lane_i32((int)b, l), hi = lane_i32((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <typename T, int CTRL>
+__device__ __forceinline__ void dpp_argmax_step(T& v, int& i) {
+    const T ov = dpp_t<CTRL>(v);
+    const int oi = dpp_i32<CTRL>(i);
+    argmax_merge(v, i, ov, oi);
+}
+
+// Arg-max over the 64 lanes of a wave (largest v, then smallest i), the
+// result in every lane.  Butterflies inside 16-lane rows by DPP (quad
+// permutations, then half-row and row mirrors), then the four row results are
+// read as scalars and merged.  Every lane of the wave must be active.
+template <typename T>
+__device__ __forceinline__ void wave_argmax_all(T& v, int& i) {
+    dpp_argmax_step<T, 0xB1>(v, i);     // quad_perm [1,0,3,2]
+    dpp_argmax_step<T, 0x4E>(v, i);     // quad_perm [2,3,0,1]
+    dpp_argmax_step<T, 0x141>(v, i);    // row_half_mirror
+    dpp_argmax_step<T, 0x140>(v, i);    // row_mirror
+    T rv = lane_t(v, 0);
+    int ri = lane_i32(i, 0);
+#pragma unroll
+    for (int r = 1; r < 4; ++r) argmax_merge(rv, ri, lane_t(v, 16 * r), lane_i32(i, 16 * r));
+    v = rv;
+    i = ri;
+}
+
 template <typename T>
 __device__ __forceinline__ void wave_argmax(T& v, int& i) {
 #pragma unroll
@@ -27,6 +70,29 @@ __device__ __forceinline__ void wave_argmax(T& v, int& i) {
         int oi = __shfl_xor(i, off, kWave);
         argmax_merge(v, i, ov, oi);
     }
+}
+
+// Work-group barrier that orders LDS accesses only.  Unlike __syncthreads()
+// it does not wait for this thread's outstanding global stores (the panel's
+// exchange words carry their own tags, so nothing read across this barrier
+// depends on them).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// OR of v over the work-group of `waves` wavefronts through LDS slots
+// slots[2][waves]; callers alternate `parity` between consecutive calls so a
+// slot is never rewritten before every wave has read it.
+__device__ __forceinline__ int wg_or(int v, int* slots, int parity, int waves) {
+    const int wave = threadIdx.x / 64;
+    const int any = __any(v & 1) | (__any(v & 2) << 1) | (__any(v & 4) << 2);
+    if ((threadIdx.x & 63) == 0) slots[parity * waves + wave] = any;
+    lds_barrier();
+    int r = 0;
+    for (int w = 0; w < waves; ++w) r |= slots[parity * waves + w];
+    return r;
 }
 
 // Device-coherent exchange words.  Agent-scope relaxed atomic loads and stores

@@ -19,39 +19,13 @@
 // schedule does) leaves the result bit-identical.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "mfma.hpp"
 
 namespace lu {
 
 namespace {
 
-typedef double v4d __attribute__((ext_vector_type(4)));
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef _Float16 v8h __attribute__((ext_vector_type(8)));
-typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
-
 constexpr int kBM = 128, kBN = 128, kThreads = 256;
-
-// Accumulator type and output lane layout of the 16x16 MFMA result D (16 x 16):
-// lane l, register r holds D[row(l, r)][l % 16] with
-//   v_mfma_f64_16x16x4f64:   row = l/16 + 4r   (measured on gfx950)
-//   v_mfma_f32_16x16x4f32:   row = 4(l/16) + r
-// With the swapped operand roles, D's rows run along C's columns.
-template <typename T> struct Acc;
-template <> struct Acc<double> {
-    typedef v4d type;
-    static __device__ __forceinline__ int col(int lg, int r) { return lg + 4 * r; }
-};
-template <> struct Acc<float> {
-    typedef v4f type;
-    static __device__ __forceinline__ int col(int lg, int r) { return 4 * lg + r; }
-};
-
-__device__ __forceinline__ v4d mfma(double a, double b, v4d c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ v4f mfma(float a, float b, v4f c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
 
 // Map the linear work-group id to a (tile_m, tile_n) pair.  Work-groups are
 // dealt to the 8 XCDs round-robin; this remap gives each XCD a contiguous

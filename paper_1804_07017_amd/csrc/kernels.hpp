@@ -49,7 +49,7 @@ struct SwapTrsmArgs {
     int w;                // panel width
     const int* moves;     // composed interchanges of the panel (rows relative to r0)
     int c0, c1;           // columns to process
-    int bn;               // columns per work-group (set by the launcher)
+    const T* linv;        // inverses of L11's 16x16 diagonal blocks (launch_diag_inv)
     H* uh;                // optional half copy of U12: uh[col*lduh + t], t = row - r0
     long long lduh;
     float* cs;            // per-column inverse scales of uh, indexed by column
@@ -57,6 +57,10 @@ struct SwapTrsmArgs {
 
 template <typename T, typename H>
 int launch_swap_trsm(const SwapTrsmArgs<T, H>& args, hipStream_t stream);
+// linv[blk*256 + k*16 + j] = inverse of the unit-lower 16x16 diagonal block
+// blk of the w x w block at (r0, r0): element (j, k).  ceil(w/16) blocks.
+template <typename T>
+int launch_diag_inv(const T* A, long long lda, int r0, int w, T* linv, hipStream_t stream);
 template <typename T>
 int launch_lswap(T* A, long long lda, int r0, const int* moves, int c0, int c1, hipStream_t stream);
 int launch_moves(const int* ipiv_rel, int w, int m, int* moves, hipStream_t stream);

@@ -85,14 +85,10 @@ template <typename T, int NB, int RPT> struct FinCfg {
 
 template <typename T, int NB, int RPT>
 struct PanelShared {
-    T red_v[kPanelThreads / kWave];
-    int red_i[kPanelThreads / kWave];
-    int win_i;
-    int win_g;
-    T drow[2 * NB];               // row d of the block, zero padded
-    T prow[2 * NB];               // pivot row of the block (block column order), zero padded;
-                                  // must follow drow directly (addressed as drow + 2*NB)
-    unsigned xbuf[kMaxPanelWgs * Xch<T, NB>::SR + Xch<T, NB>::DR];   // payloads of one step
+    T red_v[2][kPanelThreads / kWave];
+    int red_i[2][kPanelThreads / kWave];
+    int orslot[2 * (kPanelThreads / kWave)];
+    unsigned xbuf[kMaxPanelWgs * (1 + Xch<T, NB>::WPV) + 2 * Xch<T, NB>::DR];   // payloads of one step
     T fin[NB][FinCfg<T, NB, RPT>::cols];   // finished block columns of this work-group's rows
     T L[NB][NB + 1];
     T U[kMovesMaxW][NB];          // in-panel update: the block's U rows, transposed
@@ -297,7 +293,6 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
     if (g == 0 && tid == 0 && a.sync_next) {
         a.sync_next[0] = 0u;   // counter of the next launch's slot (its previous user has finished)
     }
-    if (tid < NB) { sh.prow[NB + tid] = T(0); sh.drow[NB + tid] = T(0); }
 
     auto row_of = [&](int q) { return g * R + q * kPanelThreads + tid; };
     // finished column t (< NB) of the current block, own row q
@@ -308,6 +303,16 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
     auto fin_set = [&](int t, int q, T v) {
         if constexpr (FinCfg<T, NB, RPT>::lds) sh.fin[t][q * kPanelThreads + tid] = v;
     };
+    // the same for the row of fin column `col` (= q * threads + owner thread)
+    auto fin_at = [&](int t, int col, int cb) -> T {
+        if constexpr (FinCfg<T, NB, RPT>::lds) return sh.fin[t][col];
+        else return A[min(g * R + col, m - 1) + (long long)(cb + t) * lda];
+    };
+    auto fin_set_at = [&](int t, int col, T v) {
+        if constexpr (FinCfg<T, NB, RPT>::lds) sh.fin[t][col] = v;
+    };
+    const int lane = tid & (kWave - 1);
+    const int wave = tid / kWave;
 
     for (int cb = 0; cb < w; cb += NB) {
         const int nbw = (w - cb) < NB ? (w - cb) : NB;
@@ -328,7 +333,8 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
             const int d = cb + j;
             const unsigned tag = a.tag_base + (unsigned)d;
             unsigned long long* xa = a.xch + (size_t)(d & 1) * X::PAR;     // this step's parity area
-            // 1. local arg-max of |a| over rows >= d (current column = slot 0)
+            // 1. local arg-max of |a| over rows >= d (current column = slot 0),
+            //    wave reduction, then every thread merges the wave results
             T bv = T(-1);
             int bi = 0x7fffffff;
 #pragma unroll
@@ -336,106 +342,131 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
                 const int i = row_of(q);
                 if (i >= d && i < m) argmax_merge(bv, bi, dabs(reg[q][0]), i);
             }
-            wave_argmax(bv, bi);
-            if ((tid & (kWave - 1)) == 0) { sh.red_v[tid / kWave] = bv; sh.red_i[tid / kWave] = bi; }
-            __syncthreads();
-            if (tid == 0) {
+            wave_argmax_all(bv, bi);
+            const int rpar = j & 1;                    // red slots alternate between steps
+            if ((tid & (kWave - 1)) == 0) { sh.red_v[rpar][tid / kWave] = bv; sh.red_i[rpar][tid / kWave] = bi; }
+            lds_barrier();
 #pragma unroll
-                for (int wv = 1; wv < kPanelThreads / kWave; ++wv) argmax_merge(bv, bi, sh.red_v[wv], sh.red_i[wv]);
-                sh.win_i = bi;
-                unsigned long long* slot = xa + (size_t)g * X::SW;
-                xstore(&slot[0], tagged(tag, (unsigned)bi));
-                put_value(&slot[1], bv, tag);
-            }
-            __syncthreads();
-            // 2. publish the local winner's block row and, from its owner, row d:
-            //    finished columns < j from the LDS copy, the register part at
-            //    positions j..j+NB-1 (slots hold 2*NB values)
+            for (int wv = 0; wv < kPanelThreads / kWave; ++wv) argmax_merge(bv, bi, sh.red_v[rpar][wv], sh.red_i[rpar][wv]);
+            // 2. publish: the header of this work-group's candidate (thread 0),
+            //    then the candidate's block row and row d, each by the wave that
+            //    owns the row: lane t supplies block column t (finished columns
+            //    from the LDS copy, the rest read from the owner's registers)
             {
-                const int wi = sh.win_i;
-                if (wi == 0x7fffffff && tid < NB)      // no candidate here: a zero row completes the slot
-                    put_value(&xa[(size_t)g * X::SW + 1 + X::WPV + tid * X::WPV], T(0), tag);
+                unsigned long long* slot = xa + (size_t)g * X::SW;
+                if (tid == 0) {
+                    xstore(&slot[0], tagged(tag, (unsigned)bi));
+                    put_value(&slot[1], bv, tag);
+                }
+                if (bi == 0x7fffffff && tid < NB)      // no candidate here: a zero row completes the slot
+                    put_value(&slot[1 + X::WPV + tid * X::WPV], T(0), tag);
 #pragma unroll
                 for (int q = 0; q < RPT; ++q) {
                     const int i = row_of(q);
-                    if (i == wi || i == d) {
 #pragma unroll
-                        for (int slot = 0; slot < 2; ++slot) {
-                            const bool mine = slot == 0 ? (i == wi) : (i == d);
-                            if (!mine) continue;
-                            unsigned long long* dst = slot == 0 ? xa + (size_t)g * X::SW + 1 + X::WPV
-                                                                : xa + (size_t)kMaxPanelWgs * X::SW;
-                            for (int t = 0; t < j; ++t) put_value(&dst[t * X::WPV], fin_get(t, q, cb), tag);
+                    for (int which = 0; which < 2; ++which) {
+                        const unsigned long long mask = __ballot(which == 0 ? (i == bi) : (i == d));
+                        if (mask) {
+                            const int ol = __ffsll((long long)mask) - 1;
+                            const int col = q * kPanelThreads + wave * kWave + ol;
+                            T v = (lane < j) ? fin_at(lane, col, cb) : T(0);
 #pragma unroll
-                            for (int s = 0; s < NB; ++s) put_value(&dst[(j + s) * X::WPV], reg[q][s], tag);
+                            for (int s = 0; s < NB; ++s) {
+                                const T r = lane_t(reg[q][s], ol);
+                                if (lane == j + s) v = r;
+                            }
+                            unsigned long long* dst = which == 0 ? slot + 1 + X::WPV
+                                                                 : xa + (size_t)kMaxPanelWgs * X::SW;
+                            if (lane < NB) put_value(&dst[lane * X::WPV], v, tag);
                         }
                     }
                 }
             }
-            // 3. gather every work-group's candidate and row d: poll the tagged
-            //    words until all carry this step's tag (bounded wait)
+            // 3. phase A: every work-group's header and row d, polled until all
+            //    words carry this step's tag (bounded wait); one word per thread
+            const long long t0 = wall_clock64();
+            int poll = 0;
+            bool failed = false;
             {
-                const int nslot = P * X::SR;
-                const int total = nslot + X::DR;
-                constexpr int kMaxPer = (kMaxPanelWgs * X::SR + X::DR + kPanelThreads - 1) / kPanelThreads;
-                unsigned done = 0u;                       // bit u: word tid + u*threads is in
-                const long long t0 = wall_clock64();
+                constexpr int HW = 1 + X::WPV;                         // header words per slot
+                static_assert(kMaxPanelWgs * HW + X::DR <= kPanelThreads, "one exchange word per thread");
+                const int nh = P * HW;
+                const int total = nh + X::DR;
+                const unsigned long long* src = (tid < nh)
+                    ? xa + (size_t)(tid / HW) * X::SW + (tid % HW)
+                    : xa + (size_t)kMaxPanelWgs * X::SW + (tid - nh);
+                bool done = tid >= total;
                 for (;;) {
-                    int ok = 1;
-#pragma unroll
-                    for (int u = 0; u < kMaxPer; ++u) {
-                        const int e2 = tid + u * kPanelThreads;
-                        if (e2 < total && !(done & (1u << u))) {
-                            const unsigned long long* src = (e2 < nslot)
-                                ? xa + (size_t)(e2 / X::SR) * X::SW + (e2 % X::SR)
-                                : xa + (size_t)kMaxPanelWgs * X::SW + (e2 - nslot);
-                            const unsigned long long wv = xload(src);
-                            if ((unsigned)(wv >> 32) == tag) { sh.xbuf[e2] = (unsigned)wv; done |= 1u << u; }
-                            else ok = 0;
-                        }
+                    // the data word and (thread 0) the error word are loaded together
+                    unsigned long long wv = 0;
+                    unsigned errw = 0;
+                    if (!done) wv = xload(src);
+                    if (tid == 0) errw = xload(a.sync + 1);
+                    int st = 0;
+                    if (!done) {
+                        if ((unsigned)(wv >> 32) == tag) { sh.xbuf[tid] = (unsigned)wv; done = true; }
+                        else st = 1;
                     }
                     // bit 0: some word still stale; bit 1: time limit passed or another work-group failed
-                    int st = ok ? 0 : 1;
-                    if (tid == 0 && ((wall_clock64() - t0 > a.spin_limit) || xload(a.sync + 1) != 0u)) st |= 2;
-                    st = __syncthreads_or(st);
+                    if (tid == 0 && (errw != 0u || wall_clock64() - t0 > a.spin_limit)) st |= 2;
+                    st = wg_or(st, sh.orslot, poll & 1, kPanelThreads / kWave);
+                    ++poll;
                     if (!(st & 1)) break;
-                    if (st & 2) {
-                        if (tid == 0) xstore(a.sync + 1, 1u);
-                        return;
-                    }
+                    if (st & 2) { failed = true; break; }
                 }
             }
-            // 4. global winner (same decision in every work-group)
-            if (tid < kWave) {
+            if (failed) {
+                if (tid == 0) xstore(a.sync + 1, 1u);
+                return;
+            }
+            // 4. global winner, computed by every wave from the headers (same
+            //    decision everywhere: largest magnitude, then smallest row); the
+            //    winning row's owner follows from the row distribution
+            int p, wg;
+            {
+                constexpr int HW = 1 + X::WPV;
                 T v = T(-1);
-                int i = 0x7fffffff, gg = 0x7fffffff;
-                for (int c = tid; c < P; c += kWave) {
-                    const unsigned* sw = &sh.xbuf[c * X::SR];
-                    const int ci = (int)sw[0];
-                    const T cv = get_value(&sw[1], (T*)nullptr);
-                    if (cv > v || (cv == v && ci < i)) { v = cv; i = ci; gg = c; }
+                int i = 0x7fffffff;
+                if (lane < P) {
+                    const unsigned* sw = &sh.xbuf[lane * HW];
+                    i = (int)sw[0];
+                    v = get_value(&sw[1], (T*)nullptr);
                 }
-#pragma unroll
-                for (int off = 32; off >= 1; off >>= 1) {
-                    T ov = __shfl_xor(v, off, kWave);
-                    int oi = __shfl_xor(i, off, kWave);
-                    int og = __shfl_xor(gg, off, kWave);
-                    if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; gg = og; }
+                wave_argmax_all(v, i);
+                if (i == 0x7fffffff) { p = d; wg = -1; }   // no finite candidate: keep row d
+                else { p = i; wg = i / R; }
+            }
+            // 5. phase B: the winning work-group's block row
+            const int nhw = P * (1 + X::WPV);                          // xbuf: headers, row d, winner row
+            const int ww = nhw + X::DR;
+            if (wg >= 0) {
+                bool done = tid >= X::DR;
+                for (;;) {
+                    unsigned long long wv = 0;
+                    unsigned errw = 0;
+                    if (!done) wv = xload(xa + (size_t)wg * X::SW + 1 + X::WPV + tid);
+                    if (tid == 0) errw = xload(a.sync + 1);
+                    int st = 0;
+                    if (!done) {
+                        if ((unsigned)(wv >> 32) == tag) { sh.xbuf[ww + tid] = (unsigned)wv; done = true; }
+                        else st = 1;
+                    }
+                    if (tid == 0 && (errw != 0u || wall_clock64() - t0 > a.spin_limit)) st |= 2;
+                    st = wg_or(st, sh.orslot, poll & 1, kPanelThreads / kWave);
+                    ++poll;
+                    if (!(st & 1)) break;
+                    if (st & 2) { failed = true; break; }
                 }
-                if (tid == 0) {
-                    if (i == 0x7fffffff) { i = d; gg = -1; }   // no finite candidate: keep row d
-                    sh.win_i = i;
-                    sh.win_g = gg;
+                if (failed) {
+                    if (tid == 0) xstore(a.sync + 1, 1u);
+                    return;
                 }
             }
-            __syncthreads();
-            const int p = sh.win_i;
-            const int wg = sh.win_g;
-            if (tid < NB) {
-                sh.drow[tid] = get_value(&sh.xbuf[nslot_words<X>(P) + tid * X::WPV], (T*)nullptr);
-                sh.prow[tid] = (wg >= 0) ? get_value(&sh.xbuf[wg * X::SR + 1 + X::WPV + tid * X::WPV], (T*)nullptr)
-                                         : sh.drow[tid];
-            }
+            // block-row values of row d and of the pivot row, decoded from xbuf
+            auto drow_at = [&](int t) -> T { return get_value(&sh.xbuf[nhw + t * X::WPV], (T*)nullptr); };
+            auto prow_at = [&](int t) -> T {
+                return wg >= 0 ? get_value(&sh.xbuf[ww + t * X::WPV], (T*)nullptr) : drow_at(t);
+            };
             if (tid == 0) {
                 sh.piv[d] = p;
                 if (g == 0) {
@@ -443,28 +474,47 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
                     if (a.ipiv_rel) a.ipiv_rel[d] = p;
                 }
             }
-            __syncthreads();
-            const T piv = sh.prow[j];
+            const T piv = prow_at(j);
             if (piv == T(0) && g == 0 && tid == 0 && a.info) atomicCAS(a.info, 0, a.info_col_base + d + 1);
-            // 5. rows d and p: the finished columns go to memory and to the LDS
-            //    copy (columns >= j written too are rewritten when their own step
-            //    stores them), the rest replaces the register block
+            // 6. rows d and p exchange: the owner's wave writes the block row
+            //    to memory and the finished columns to the LDS copy, the owner
+            //    lane reloads its register block (columns >= j written to
+            //    memory here are rewritten when their own step stores them)
             if (p != d) {
 #pragma unroll
                 for (int q = 0; q < RPT; ++q) {
                     const int i = row_of(q);
-                    if (i == p || i == d) {
-                        const int so = (i == p) ? 0 : 2 * NB;       // sh.drow | sh.prow
-                        const T* src = sh.drow + so;
 #pragma unroll
-                        for (int t = 0; t < NB; ++t) A[i + (long long)(cb + min(t, nbw - 1)) * lda] = src[min(t, nbw - 1)];
-                        for (int t = 0; t < j; ++t) fin_set(t, q, src[t]);
+                    for (int which = 0; which < 2; ++which) {     // 0: row p takes row d; 1: row d takes row p
+                        const unsigned long long mask = __ballot(i == (which == 0 ? p : d));
+                        if (mask) {
+                            const int ol = __ffsll((long long)mask) - 1;
+                            const int col = q * kPanelThreads + wave * kWave + ol;
+                            const int row = g * R + col;
+                            if (lane < nbw) {
+                                const T v = which == 0 ? drow_at(lane) : prow_at(lane);
+                                A[row + (long long)(cb + lane) * lda] = v;
+                                if (lane < j) fin_set_at(lane, col, v);
+                            }
+                            if (lane == ol) {
 #pragma unroll
-                        for (int s = 0; s < NB; ++s) reg[q][s] = src[j + s];
+                                for (int s = 0; s < NB; ++s) {
+                                    const int t = min(j + s, NB - 1);
+                                    const T v = which == 0 ? drow_at(t) : prow_at(t);
+                                    reg[q][s] = (j + s < NB) ? v : T(0);
+                                }
+                            }
+                        }
                     }
                 }
             }
-            // 6. scale, rank-1 update, store column j, shift
+            // 7. scale, rank-1 update, store column j, shift
+            T pr[NB];
+#pragma unroll
+            for (int s = 1; s < NB; ++s) {
+                const int t = min(j + s, NB - 1);
+                pr[s] = (j + s < NB) ? prow_at(t) : T(0);
+            }
 #pragma unroll
             for (int q = 0; q < RPT; ++q) {
                 const int i = row_of(q);
@@ -473,7 +523,7 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
                     if (piv != T(0)) l = l / piv;
                     reg[q][0] = l;
 #pragma unroll
-                    for (int s = 1; s < NB; ++s) reg[q][s] = reg[q][s] - l * sh.prow[j + s];
+                    for (int s = 1; s < NB; ++s) reg[q][s] = reg[q][s] - l * pr[s];
                 }
                 if (i < m) A[i + (long long)d * lda] = reg[q][0];
                 fin_set(j, q, reg[q][0]);
@@ -481,6 +531,8 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
                 for (int s = 0; s + 1 < NB; ++s) reg[q][s] = reg[q][s + 1];
                 reg[q][NB - 1] = T(0);
             }
+            // (the next step's phase A rewrites xbuf only after its first barrier,
+            // which every wave reaches after its last read of this step's xbuf)
         }
 
         const bool more_cols = (w - cb - nbw) > 0 || cb > 0;

@@ -1,5 +1,8 @@
 // Look-ahead schedule: the task DAG of the blocked right-looking LU and its
-// placement on two streams (paper Sec. 3.3 Listing 3, Sec. 4 Listing 5).
+// placement on streams (paper Sec. 3.3 Listing 3, Sec. 4 Listing 5): stream 0
+// runs the bulk trailing update, stream 1 the look-ahead panel work, stream 2
+// the interchanges of finished columns left of each panel (off the critical
+// path; nothing reads those columns again before the end).
 //
 // The program order built here is itself a valid sequential order of the
 // algorithm; stream placement only adds concurrency.  Cross-stream waits are
@@ -96,26 +99,31 @@ int build_plan(int n, int b, int depth, std::vector<PlanTask>& out) {
                 for (int i = k + 1; i < j; ++i) push(kTaskUpdate, i, c0, c1, 1);
                 push(kTaskPanel, j, c0, c1, 1);
             }
-            if (k >= 1) push(kTaskLswap, k, 0, k * b, 0);
+            if (k >= 1) push(kTaskLswap, k, 0, k * b, 2);
         }
     }
     // Derive cross-stream waits from data accesses.
     const int T = (int)out.size();
     std::vector<Access> acc(T);
     for (int i = 0; i < T; ++i) acc[i] = access_of(out[i], b, n);
-    int covered[2] = {-1, -1};   // covered[s]: latest task of stream 1-s known done by stream s
+    // covered[s][u]: latest task of stream u that stream s already waits for
+    int covered[kPlanStreams][kPlanStreams];
+    for (auto& r : covered) for (int& c : r) c = -1;
     for (int i = 0; i < T; ++i) {
         PlanTask& t = out[i];
         const int s = t.stream;
-        int need = -1;
-        for (int e = i - 1; e > covered[s]; --e) {
-            if (out[e].stream == s) continue;
-            if (conflicts(acc[e], acc[i])) { need = e; break; }
-        }
-        if (need >= 0) {
-            t.wait[t.nwait++] = need;
-            out[need].record = 1;
-            covered[s] = need;
+        for (int u = 0; u < kPlanStreams; ++u) {
+            if (u == s) continue;
+            int need = -1;
+            for (int e = i - 1; e > covered[s][u]; --e) {
+                if (out[e].stream != u) continue;
+                if (conflicts(acc[e], acc[i])) { need = e; break; }
+            }
+            if (need >= 0) {
+                t.wait[t.nwait++] = need;
+                out[need].record = 1;
+                covered[s][u] = need;
+            }
         }
     }
     return T;

@@ -7,6 +7,7 @@
 namespace lu {
 
 enum { kTaskPanel = LU_TASK_PANEL, kTaskUpdate = LU_TASK_UPDATE, kTaskLswap = LU_TASK_LSWAP };
+constexpr int kPlanStreams = LU_PLAN_STREAMS;
 
 struct PlanTask {
     int kind, step, col_begin, col_end, stream;

@@ -30,6 +30,7 @@ struct DeviceState {
     long long spin_limit = 0;          // ~2 s of the device wall clock
     int panel_occupancy = 1;           // panel kernel register budget variant (LU_PANEL_OCC)
     hipStream_t panel_stream = nullptr;
+    hipStream_t swap_stream = nullptr;   // interchanges of finished columns (off the critical path)
     std::vector<hipEvent_t> events;    // ring used for cross-stream dependencies
     int ev_next = 0;
 
@@ -39,6 +40,7 @@ struct DeviceState {
     unsigned panel_launches = 0;       // numbers the panel launches (exchange tags)
     Buffer cand;                       // candidate exchange area of the panel kernel
     Buffer moves;                      // per-panel composed interchanges
+    Buffer linv;                       // per-panel inverses of the 16x16 diagonal L blocks
     int* info = nullptr;               // library INFO word
     hipStream_t last_stream = nullptr; // stream of the last factorization
     int* last_info = nullptr;

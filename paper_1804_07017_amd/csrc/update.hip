@@ -2,19 +2,22 @@
 // (paper Sec. 3.4: laswp and trsm of getrf; Sec. 3.5: RL2 of LU_blk,
 // A12 := trilu(A11)^-1 A12, trilu = the unit lower triangle).
 //
-// swap_trsm_kernel: one work-group per BN columns of the trailing block.
-//   1. gather: the w top rows of its columns into LDS, with the panel's
-//      composed interchanges applied (rows that received another row's data
-//      read it from that row); the extra rows (interchange targets below the
-//      top w rows) are read too and written back only after every read of
-//      the work-group's columns is done;
-//   2. forward substitution with the unit lower w x w block L11, staged in
-//      LDS by column chunks;
-//   3. the U12 rows go back to the matrix (and, in the mixed-precision mode,
-//      to a half-precision copy with one power-of-two scale per column).
+// swap_trsm_kernel: LASWP and RL2 (A12 := trilu(A11)^-1 A12, paper Sec. 3.5)
+// for one slab of BN columns per work-group:
+//   1. gather: the w top rows of the slab, with the panel's composed
+//      interchanges applied, straight into matrix-core accumulators; then the
+//      rows displaced below the top w rows are written out (every read of the
+//      slab is done by then);
+//   2. blocked forward substitution with 16-row blocks: block row i is
+//      finished as X_i = inv(L_ii) X_i (the 16x16 unit-lower inverses come from
+//      diag_inv_kernel), then every block row below takes X_j -= L_ji X_i --
+//      both on the FP64/FP32 matrix cores, X staying in registers;
+//   3. U12 goes back to the matrix (and, in the mixed-precision mode, to a
+//      half-precision copy with one power-of-two scale per column).
 // lswap_kernel: the same interchanges on finished columns left of the panel.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "mfma.hpp"
 
 namespace lu {
 
@@ -33,144 +36,250 @@ __device__ __forceinline__ float pow2_scale(float amax) {
     return ldexpf(1.f, 15 - e);          // amax * 2^(15-e) in [2^14, 2^15)
 }
 
-template <typename T, typename H>
-__global__ __launch_bounds__(kThreads) void swap_trsm_kernel(SwapTrsmArgs<T, H> a) {
-    extern __shared__ unsigned char smem_raw[];
-    const int w = a.w, BN = a.bn;
-    const int ldx = BN + 1;
-    T* X = reinterpret_cast<T*>(smem_raw);              // [w][BN+1] the top rows
-    T* V = X + (size_t)w * ldx;                         // [w][BN]  extra-row values, later L chunks
+// Inverses of the 16x16 unit-lower diagonal blocks of L11 (w x w at (r0, r0)):
+// linv[blk*256 + k*16 + j] = inv(L_blk)[j][k] (column-major blocks); rows and
+// columns past w are taken from the identity.  One 64-thread work-group per
+// block; lane j < 16 solves for column j.
+template <typename T>
+__global__ __launch_bounds__(64) void diag_inv_kernel(const T* __restrict__ A, long long lda, int r0, int w,
+                                                      T* __restrict__ linv) {
+    __shared__ T Lb[16][17];
+    __shared__ T Y[16][17];
+    const int blk = blockIdx.x, l = threadIdx.x;
+    const int b0 = blk * 16;
+    for (int e = l; e < 256; e += 64) {
+        const int i = e % 16, k = e / 16;
+        const bool in = b0 + i < w && b0 + k < w && i > k;
+        Lb[i][k] = in ? A[(r0 + b0 + i) + (long long)(r0 + b0 + k) * lda] : T(0);
+    }
+    __syncthreads();
+    if (l < 16) {
+        const int j = l;
+        for (int r = 0; r < 16; ++r) Y[r][j] = (r == j) ? T(1) : T(0);
+        for (int r = j + 1; r < 16; ++r) {
+            T acc = T(0);
+            for (int q = j; q < r; ++q) acc += Lb[r][q] * Y[q][j];
+            Y[r][j] = -acc;
+        }
+    }
+    __syncthreads();
+    for (int e = l; e < 256; e += 64) {
+        const int j = e % 16, k = e / 16;           // inv[j][k] at k*16 + j
+        linv[(size_t)blk * 256 + e] = Y[j][k];
+    }
+}
+
+// ROWT row tiles (16 rows each) per wave, NCT column tiles (16 columns) per
+// work-group; wave v owns row tiles v, v+4, v+8, ...
+template <typename T, typename H, int ROWT, int NCT>
+__global__ __launch_bounds__(kThreads, 2) void swap_trsm_kernel(SwapTrsmArgs<T, H> a) {
+    typedef typename Acc<T>::type V4;
+    constexpr int BN = 16 * NCT;
+    constexpr int LDX = BN + 1;
+    __shared__ int top_src[kMovesMaxW];
+    __shared__ int ex_dst[kMovesMaxW];
+    __shared__ int ex_src[kMovesMaxW];
+    __shared__ T Xi[2][16][LDX];       // finished block row i (double-buffered)
+    __shared__ T Ys[16][LDX];          // owner's staging of block row i before inv(L_ii)
+    __shared__ unsigned colmax[BN];
 
     const int tid = threadIdx.x;
+    const int wave = tid / 64, lane = tid % 64;
+    const int l16 = lane % 16, lg = lane / 16;
+    const int w = a.w;
+    const int nrt = (w + 15) / 16;
     const int c_base = a.c0 + blockIdx.x * BN;
-    const int nc = min(BN, a.c1 - c_base);
     const long long lda = a.lda;
     T* __restrict__ Atop = a.A + a.r0;                  // row r0 of column 0
-    __shared__ int mv[2 * 2 * kMovesMaxW];   // (dst, src): top moves, then extra moves
-    const int ntop = a.moves[0], nex = a.moves[1];
-    for (int s = tid; s < ntop; s += kThreads) { mv[2 * s] = a.moves[2 + 2 * s]; mv[2 * s + 1] = a.moves[3 + 2 * s]; }
-    for (int s = tid; s < nex; s += kThreads) {
-        mv[2 * (ntop + s)] = a.moves[kMovesExtra + 2 * s];
-        mv[2 * (ntop + s) + 1] = a.moves[kMovesExtra + 1 + 2 * s];
-    }
-
-    // 1. gather (reads only), batched so that many loads are in flight
-    constexpr int kBatch = 8;
-    for (int e0 = tid; e0 < w * BN; e0 += kThreads * kBatch) {
-        T v[kBatch];
-#pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            const int e = e0 + u * kThreads;
-            const int t = e % w, c = e / w;
-            v[u] = (e < w * BN && c < nc) ? Atop[t + (long long)(c_base + c) * lda] : T(0);
-        }
-#pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            const int e = e0 + u * kThreads;
-            if (e < w * BN) X[(e % w) * ldx + e / w] = v[u];
-        }
-    }
-    __syncthreads();
-    const int cnt = ntop + nex;
-    for (int e0 = tid; e0 < cnt * BN; e0 += kThreads * kBatch) {
-        T v[kBatch];
-#pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            const int e = e0 + u * kThreads;
-            const int s = e / BN, c = e % BN;
-            v[u] = (e < cnt * BN && c < nc) ? Atop[mv[2 * s + 1] + (long long)(c_base + c) * lda] : T(0);
-        }
-#pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            const int e = e0 + u * kThreads;
-            if (e < cnt * BN) {
-                const int s = e / BN, c = e % BN;
-                if (s < ntop) X[mv[2 * s] * ldx + c] = v[u];
-                else V[(s - ntop) * BN + c] = v[u];
-            }
-        }
-    }
-    __syncthreads();
-    // scatter of the extra rows, after every read of these columns
-    for (int e = tid; e < nex * BN; e += kThreads) {
-        const int s = e / BN, c = e % BN;
-        if (c < nc) Atop[mv[2 * (ntop + s)] + (long long)(c_base + c) * lda] = V[s * BN + c];
-    }
-    __syncthreads();
-
-    // 2. forward substitution with unit-lower L11 in blocks of KB rows:
-    //    (a) the KB x KB diagonal block, one thread per column;
-    //    (b) the rows below, X[i] -= L[i, blk] X[blk], all threads.
-    //    L11's block columns are staged into V (w x BN values >= (w-k0) x KB);
-    //    the next block's columns are loaded into registers while the current
-    //    block is being solved, so their latency is hidden.
-    constexpr int kPre = 16;                      // staged values per thread per block
-    // KB <= BN (V capacity) and w*KB <= kPre*256 (register prefetch capacity)
-    const int KB = min(min(BN, 16), (kPre * kThreads) / w);
     const T* __restrict__ L = a.A + a.r0 + (long long)a.r0 * lda;   // L11 at (r0, r0)
-    T pre[kPre];
-    auto fetch = [&](int k0) {
-        const int rows = w - k0, kb = min(KB, w - k0);
+
+    const int ntop = a.moves[0], nex = a.moves[1];
+    for (int t = tid; t < w; t += kThreads) top_src[t] = t;
+    __syncthreads();
+    for (int s = tid; s < ntop; s += kThreads) top_src[a.moves[2 + 2 * s]] = a.moves[3 + 2 * s];
+    for (int s = tid; s < nex; s += kThreads) {
+        ex_dst[s] = a.moves[kMovesExtra + 2 * s];
+        ex_src[s] = a.moves[kMovesExtra + 1 + 2 * s];
+    }
+    if (tid < BN) colmax[tid] = 0u;
+    __syncthreads();
+
+    // 1. gather into the accumulators: lane (l16, lg), register r of tile
+    //    (q, ct) holds X[row = (wave + 4q)*16 + l16][col = ct*16 + Acc::col(lg, r)]
+    V4 acc[ROWT][NCT];
 #pragma unroll
-        for (int u = 0; u < kPre; ++u) {
-            const int e = tid + u * kThreads;
-            const int i = e % rows, s = e / rows;
-            const bool ok = e < rows * kb;
-            pre[u] = L[(k0 + (ok ? i : 0)) + (long long)(k0 + (ok ? s : 0)) * lda];
-        }
-    };
-    auto stage = [&](int k0) {
-        const int rows = w - k0, kb = min(KB, w - k0);
+    for (int q = 0; q < ROWT; ++q) {
+        const int t = (wave + 4 * q) * 16 + l16;
+        const bool rok = t < w;
+        const int src = rok ? top_src[t] : 0;
 #pragma unroll
-        for (int u = 0; u < kPre; ++u) {
-            const int e = tid + u * kThreads;
-            if (e < rows * kb) V[(e % rows) * KB + e / rows] = pre[u];
-        }
-    };
-    fetch(0);
-    for (int k0 = 0; k0 < w; k0 += KB) {
-        const int kb = min(KB, w - k0);
-        const int rows = w - k0;
-        stage(k0);
-        __syncthreads();
-        if (k0 + KB < w) fetch(k0 + KB);
-        if (tid < BN) {
-            const int c = tid;
-            for (int s = 0; s < kb; ++s) {
-                const T xs = X[(k0 + s) * ldx + c];
-                for (int r = s + 1; r < kb; ++r) X[(k0 + r) * ldx + c] -= V[r * KB + s] * xs;
+        for (int ct = 0; ct < NCT; ++ct) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int col = c_base + ct * 16 + Acc<T>::col(lg, r);
+                const bool ok = rok && col < a.c1;
+                const T v = Atop[src + (long long)(ok ? col : a.c0) * lda];
+                acc[q][ct][r] = ok ? v : T(0);
             }
         }
-        __syncthreads();
-        const int below = rows - kb;
-        for (int e = tid; e < below * BN; e += kThreads) {
-            const int ii = kb + e / BN, c = e % BN;
-            T acc = X[(k0 + ii) * ldx + c];
-#pragma unroll 4
-            for (int s = 0; s < kb; ++s) acc -= V[ii * KB + s] * X[(k0 + s) * ldx + c];
-            X[(k0 + ii) * ldx + c] = acc;
+    }
+    __syncthreads();   // every read of the slab's moved rows is done
+    // displaced top rows -> their rows below the top block (sources are
+    // original top rows, not written before step 3)
+    {
+        constexpr int kB = 8;
+        for (int e0 = tid; e0 < nex * BN; e0 += kThreads * kB) {
+            T v[kB];
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                const int e = e0 + u * kThreads;
+                const int s = e % max(nex, 1), c = c_base + e / max(nex, 1);
+                const bool ok = e < nex * BN && c < a.c1;
+                v[u] = Atop[(ok ? ex_src[s] : 0) + (long long)(ok ? c : a.c0) * lda];
+            }
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                const int e = e0 + u * kThreads;
+                const int s = e % max(nex, 1), c = c_base + e / max(nex, 1);
+                if (e < nex * BN && c < a.c1) Atop[ex_dst[s] + (long long)c * lda] = v[u];
+            }
+        }
+    }
+
+    // 2. blocked substitution; the L operand of the next step is prefetched
+    //    into registers while the current step runs.
+    //    lane l supplies L[row = rt*16 + l16][k = 16 i + 4 kk + lg]
+    auto load_l = [&](int i, T (&dst)[ROWT][4]) {
+#pragma unroll
+        for (int q = 0; q < ROWT; ++q) {
+            const int row = (wave + 4 * q) * 16 + l16;
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int k = 16 * i + 4 * kk + lg;
+                const bool ok = row < w && k < w && (wave + 4 * q) > i;
+                const T v = L[(ok ? row : 0) + (long long)(ok ? k : 0) * lda];
+                dst[q][kk] = ok ? v : T(0);
+            }
+        }
+    };
+    // The owner of block row i+1 updates it with X_i and finishes it first
+    // (the next step's critical path), then every wave updates its other rows.
+    auto load_inv = [&](int i, T (&dst)[4]) {
+        const T* __restrict__ inv = a.linv + (size_t)min(i, nrt - 1) * 256;
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) dst[kk] = inv[(4 * kk + lg) * 16 + l16];   // B[k][j] = inv[j][k]
+    };
+    // finish block row i held in acc[i/4] of the calling wave: X_i = inv(L_ii) X_i
+    auto finish = [&](int i, const T (&bi)[4]) {
+        const int qi = i >> 2;
+        const int buf = i & 1;
+#pragma unroll
+        for (int q = 0; q < ROWT; ++q) {
+            if (q == qi) {
+#pragma unroll
+                for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) Ys[l16][ct * 16 + Acc<T>::col(lg, r)] = acc[q][ct][r];
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);      // lgkmcnt(0): the wave's LDS writes are done
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+            V4 d = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) d = mfma(Ys[4 * kk + lg][ct * 16 + l16], bi[kk], d);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Xi[buf][l16][ct * 16 + Acc<T>::col(lg, r)] = d[r];
+#pragma unroll
+            for (int q = 0; q < ROWT; ++q)
+                if (q == qi) acc[q][ct] = d;
+        }
+    };
+    auto update = [&](int q, int buf, const T (&l)[4]) {
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+                acc[q][ct] = mfma(-Xi[buf][4 * kk + lg][ct * 16 + l16], l[kk], acc[q][ct]);
+    };
+    T lc[ROWT][4], ln[ROWT][4];
+    T ic[4], in_[4];
+    load_l(0, lc);
+    load_inv(0, ic);
+    if (wave == 0) finish(0, ic);
+    load_inv(1, ic);
+    __syncthreads();
+    for (int i = 0; i < nrt; ++i) {
+        const int buf = i & 1;
+        if (i + 1 < nrt) load_l(i + 1, ln);
+        if (i + 2 < nrt) load_inv(i + 2, in_);
+        const int nxt = i + 1;
+        const bool owner = nxt < nrt && wave == (nxt & 3);
+        if (owner) {
+#pragma unroll
+            for (int q = 0; q < ROWT; ++q)
+                if (q == (nxt >> 2)) update(q, buf, lc[q]);
+            finish(nxt, ic);
+        }
+#pragma unroll
+        for (int q = 0; q < ROWT; ++q) {
+            const int rt = wave + 4 * q;
+            if (rt > i && rt < nrt && !(owner && q == (nxt >> 2))) update(q, buf, lc[q]);
         }
         __syncthreads();
+#pragma unroll
+        for (int q = 0; q < ROWT; ++q)
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) lc[q][kk] = ln[q][kk];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) ic[kk] = in_[kk];
     }
-    // 3. U12 back to the matrix (and the scaled half copy)
-    for (int e = tid; e < w * BN; e += kThreads) {
-        const int t = e % w, c = e / w;
-        if (c < nc) Atop[t + (long long)(c_base + c) * lda] = X[t * ldx + c];
+
+    // 3. U12 back to the matrix
+#pragma unroll
+    for (int q = 0; q < ROWT; ++q) {
+        const int t = (wave + 4 * q) * 16 + l16;
+        if (t < w) {
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int col = c_base + ct * 16 + Acc<T>::col(lg, r);
+                    if (col < a.c1) Atop[t + (long long)col * lda] = acc[q][ct][r];
+                }
+        }
     }
     if (a.uh) {
-        __shared__ float s_scale[64];
-        if (tid < BN) {
-            float amax = 0.f;
-            for (int t = 0; t < w; ++t) amax = fmaxf(amax, fabsf((float)X[t * ldx + tid]));
-            const float sc = pow2_scale(amax);
-            s_scale[tid] = sc;
-            if (tid < nc) a.cs[c_base + tid] = 1.f / sc;
-        }
+        // per-column amax over the w rows -> power-of-two scale -> half copy
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float m = 0.f;
+#pragma unroll
+                for (int q = 0; q < ROWT; ++q)
+                    if ((wave + 4 * q) * 16 + l16 < w) m = fmaxf(m, fabsf((float)acc[q][ct][r]));
+#pragma unroll
+                for (int off = 8; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+                if (l16 == 0) atomicMax(&colmax[ct * 16 + Acc<T>::col(lg, r)], __float_as_uint(m));
+            }
         __syncthreads();
-        for (int e = tid; e < w * BN; e += kThreads) {
-            const int t = e % w, c = e / w;
-            if (c < nc) a.uh[(long long)(c_base + c) * a.lduh + t] = (H)((float)X[t * ldx + c] * s_scale[c]);
-        }
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int cc = ct * 16 + Acc<T>::col(lg, r);
+                const int col = c_base + cc;
+                if (col >= a.c1) continue;
+                const float sc = pow2_scale(__uint_as_float(colmax[cc]));
+                if (wave == 0 && l16 == 0) a.cs[col] = 1.f / sc;
+#pragma unroll
+                for (int q = 0; q < ROWT; ++q) {
+                    const int t = (wave + 4 * q) * 16 + l16;
+                    if (t < w) a.uh[(long long)col * a.lduh + t] = (H)((float)acc[q][ct][r] * sc);
+                }
+            }
     }
 }
 
@@ -298,19 +407,34 @@ template int launch_cols_half<_Float16>(const float*, long long, int, int, _Floa
 template int launch_cols_half<__bf16>(const float*, long long, int, int, __bf16*, long long, float*, hipStream_t);
 
 template <typename T, typename H>
-int launch_swap_trsm(const SwapTrsmArgs<T, H>& args0, hipStream_t stream) {
-    SwapTrsmArgs<T, H> args = args0;
+int launch_swap_trsm(const SwapTrsmArgs<T, H>& args, hipStream_t stream) {
     if (args.c1 <= args.c0 || args.w <= 0) return 0;
-    // X and V each hold w x BN values: keep them within 64 KiB together
-    int bn = (int)(32768 / (sizeof(T) * args.w));
-    if (bn > 64) bn = 64;
-    if (bn < 1) bn = 1;
-    args.bn = bn;
-    const size_t smem = (size_t)args.w * (2 * bn + 1) * sizeof(T);
-    const int grid = (args.c1 - args.c0 + bn - 1) / bn;
-    hipLaunchKernelGGL((swap_trsm_kernel<T, H>), dim3(grid), dim3(kThreads), smem, stream, args);
+    if (args.w > kMovesMaxW || !args.linv) return -1;
+    const int nrt = (args.w + 15) / 16;
+    const int ncols = args.c1 - args.c0;
+    auto go = [&](auto kern, int bn) {
+        hipLaunchKernelGGL(kern, dim3((ncols + bn - 1) / bn), dim3(kThreads), 0, stream, args);
+    };
+    if (nrt <= 4) go(swap_trsm_kernel<T, H, 1, 4>, 64);
+    else if (nrt <= 8) go(swap_trsm_kernel<T, H, 2, 4>, 64);
+    else if constexpr (sizeof(T) == 4) {  // FP32 accumulators are half the size: wider slabs
+        if (nrt <= 16) go(swap_trsm_kernel<T, H, 4, 4>, 64);
+        else go(swap_trsm_kernel<T, H, 8, 2>, 32);
+    } else {
+        if (nrt <= 16) go(swap_trsm_kernel<T, H, 4, 2>, 32);
+        else go(swap_trsm_kernel<T, H, 8, 1>, 16);
+    }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
+
+template <typename T>
+int launch_diag_inv(const T* A, long long lda, int r0, int w, T* linv, hipStream_t stream) {
+    if (w <= 0) return 0;
+    hipLaunchKernelGGL((diag_inv_kernel<T>), dim3((w + 15) / 16), dim3(64), 0, stream, A, lda, r0, w, linv);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+template int launch_diag_inv<double>(const double*, long long, int, int, double*, hipStream_t);
+template int launch_diag_inv<float>(const float*, long long, int, int, float*, hipStream_t);
 
 template <typename T>
 int launch_lswap(T* A, long long lda, int r0, const int* moves, int c0, int c1, hipStream_t stream) {

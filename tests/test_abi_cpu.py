@@ -86,7 +86,7 @@ def _access(t, b, n):
 def _happens_before(tasks):
     T = len(tasks)
     before = [set() for _ in range(T)]
-    last = {0: None, 1: None}
+    last = {s: None for s in range(3)}
     for i, t in enumerate(tasks):
         s = t["stream"]
         if last[s] is not None:
@@ -120,6 +120,11 @@ def test_plan_is_race_free_and_complete(n, b, depth):
         assert all(t["stream"] == 0 for t in tasks)
     else:
         assert all(t["stream"] == 1 for t in tasks if t["kind"] == lu.LU_TASK_PANEL)
+        assert all(t["stream"] == 2 for t in tasks if t["kind"] == lu.LU_TASK_LSWAP)
+    for t in tasks:
+        # at most one wait per other stream, each on an earlier task of another stream
+        assert len(t["waits"]) == len({tasks[w]["stream"] for w in t["waits"]})
+        assert all(tasks[w]["stream"] != t["stream"] for w in t["waits"])
     # race freedom: tasks not ordered by happens-before touch disjoint data
     hb = _happens_before(tasks)
     acc = [_access(t, b, n) for t in tasks]
@@ -166,12 +171,11 @@ def _run_task(A, ipiv, t, b, n):
 
 
 def _random_legal_order(tasks, rng):
-    q = {0: [i for i, t in enumerate(tasks) if t["stream"] == 0],
-         1: [i for i, t in enumerate(tasks) if t["stream"] == 1]}
+    q = {s: [i for i, t in enumerate(tasks) if t["stream"] == s] for s in range(3)}
     done = set()
     order = []
-    while q[0] or q[1]:
-        ready = [s for s in (0, 1) if q[s] and all(w in done for w in tasks[q[s][0]]["waits"])]
+    while any(q.values()):
+        ready = [s for s in range(3) if q[s] and all(w in done for w in tasks[q[s][0]]["waits"])]
         assert ready, "plan deadlocks"
         s = ready[rng.integers(len(ready))]
         i = q[s].pop(0)
