@@ -26,6 +26,7 @@
 // left-swap kernels.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "mfma.hpp"
 
 namespace lu {
 
@@ -33,7 +34,6 @@ namespace {
 
 constexpr int kPanelThreads = 256;    // threads per panel work-group
 constexpr int kMaxPanelWgs = kPanelMaxWgs;
-constexpr int kUChunk = 8;    // right-hand columns per pipelined pass of the in-panel update
 
 // Tagged exchange words: every published value is split into 32-bit payloads,
 // each paired with the 32-bit tag of the column step in one 64-bit word that is
@@ -203,73 +203,84 @@ __device__ __forceinline__ void block_swap_trsm(T* A, long long lda, int w, int 
     }
 }
 
-// Row i of the in-panel trailing update for one chunk of right-hand columns:
-// A[i, c0:c0+nc] -= L[i, cb:cb+nbw] U[cb:cb+nbw, c0:c0+nc], U staged in LDS
-// (U is staged transposed).
+// In-panel trailing update of one work-group's rows after a block:
+// A[i, right0 + c] -= sum_k L[i, cb + k] U[cb + k, right0 + c] for the rows
+// i >= right0 of the work-group and c < ncols, on the matrix cores (K = NB = 16,
+// four 4-deep MFMA steps per 16 x 16 tile).  Wave v takes the tiles of the
+// rows its own lanes hold (row = g*R + q*threads + v*64 + 16 rb + l16); the
+// L fragments come from the LDS copy of the finished columns (or from memory
+// when that copy does not fit), the U fragments from LDS (staged transposed,
+// zero past ncols), and each C tile is loaded, updated and stored once.
 template <typename T, int NB, int RPT>
-__device__ __forceinline__ void inpanel_update(T* A, long long lda, const int* rows, int cb, int nbw, int right0,
-                                               int ncols, const T (*U)[NB], const T (*fin)[FinCfg<T, NB, RPT>::cols]) {
-    // All of the thread's rows (rows[q] < 0: none) are updated together, a
-    // chunk of kUChunk columns at a time, with the next chunk's loads in flight
-    // while the current one is computed and stored.  Addresses are clamped into
-    // the valid range so that every load is unconditional.
-    bool act[RPT];
-    const T* rp[RPT];
-    T l[RPT][NB];
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-        act[q] = rows[q] >= 0;
-        rp[q] = A + (act[q] ? rows[q] : 0);
-#pragma unroll
-        for (int s = 0; s < NB; ++s) {
-            T v;
-            if constexpr (FinCfg<T, NB, RPT>::lds) v = fin[s][q * kPanelThreads + threadIdx.x];
-            else v = rp[q][(long long)(cb + min(s, nbw - 1)) * lda];
-            l[q][s] = (s < nbw) ? v : T(0);
-        }
-    }
-    T x[RPT][kUChunk], y[RPT][kUChunk];
+__device__ __forceinline__ void inpanel_update(T* A, long long lda, int g, int m, int cb, int nbw, int right0,
+                                               int ncols, const T (*U)[NB],
+                                               const T (*fin)[FinCfg<T, NB, RPT>::cols]) {
+    static_assert(NB == 16, "one 16-deep k block per update");
+    typedef typename Acc<T>::type V4;
+    constexpr int R = kPanelThreads * RPT;
+    const int tid = threadIdx.x;
+    const int wave = tid / kWave, lane = tid % kWave, l16 = lane % 16, lg = lane / 16;
+    // -L fragments: lf[q][rb][ks] = -L[row(q, rb, l16)][4 ks + lg]
+    T lf[RPT][4][4];
 #pragma unroll
     for (int q = 0; q < RPT; ++q)
 #pragma unroll
-        for (int cc = 0; cc < kUChunk; ++cc) x[q][cc] = rp[q][(long long)(right0 + min(cc, ncols - 1)) * lda];
-    for (int c0 = 0; c0 < ncols; c0 += kUChunk) {
-        const int nxt = c0 + kUChunk;
+        for (int rb = 0; rb < 4; ++rb) {
+            const int loc = q * kPanelThreads + wave * kWave + rb * 16 + l16;
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const int k = 4 * ks + lg;
+                T v;
+                if constexpr (FinCfg<T, NB, RPT>::lds) v = fin[k][loc];
+                else v = A[min(g * R + loc, m - 1) + (long long)(cb + k) * lda];
+                lf[q][rb][ks] = (k < nbw) ? -v : T(0);
+            }
+        }
+    const int nct = (ncols + 15) / 16;
+    // C tiles of column tile ct
+    auto load_c = [&](int ct, V4 (&c)[RPT][4]) {
 #pragma unroll
         for (int q = 0; q < RPT; ++q)
 #pragma unroll
-            for (int cc = 0; cc < kUChunk; ++cc) y[q][cc] = rp[q][(long long)(right0 + min(nxt + cc, ncols - 1)) * lda];
+            for (int rb = 0; rb < 4; ++rb) {
+                const int row = g * R + q * kPanelThreads + wave * kWave + rb * 16 + l16;
+                const bool rok = row >= right0 && row < m && ct < nct;
 #pragma unroll
-        for (int cc = 0; cc < kUChunk; ++cc) {
-            const T* Uc = &U[min(c0 + cc, ncols - 1)][0];   // U is staged transposed: U[col][s]
-#pragma unroll
-            for (int q = 0; q < RPT; ++q) {
-                T acc = x[q][cc];
-#pragma unroll
-                for (int s = 0; s < NB; ++s) acc = acc - l[q][s] * Uc[s];
-                x[q][cc] = acc;
-            }
-        }
-        const int nc = min(kUChunk, ncols - c0);
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-            if (!act[q]) continue;
-            if (nc == kUChunk) {
-#pragma unroll
-                for (int cc = 0; cc < kUChunk; ++cc) A[rows[q] + (long long)(right0 + c0 + cc) * lda] = x[q][cc];
-            } else {
-                for (int cc = 0; cc < nc; ++cc) {
-                    T v = x[q][0];
-#pragma unroll
-                    for (int k = 1; k < kUChunk; ++k) v = (cc == k) ? x[q][k] : v;
-                    A[rows[q] + (long long)(right0 + c0 + cc) * lda] = v;
+                for (int r = 0; r < 4; ++r) {
+                    const int cc = ct * 16 + Acc<T>::col(lg, r);
+                    const bool ok = rok && cc < ncols;
+                    const T v = A[(ok ? row : right0) + (long long)(right0 + (ok ? cc : 0)) * lda];
+                    c[q][rb][r] = ok ? v : T(0);
                 }
             }
+    };
+    for (int ct = 0; ct < nct; ++ct) {
+        V4 cur[RPT][4];
+        load_c(ct, cur);
+        T uf[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int k = 4 * ks + lg, c = ct * 16 + l16;
+            uf[ks] = (c < ncols) ? U[c][k] : T(0);      // U[.][k] is 0 for k >= nbw
         }
 #pragma unroll
         for (int q = 0; q < RPT; ++q)
 #pragma unroll
-            for (int cc = 0; cc < kUChunk; ++cc) x[q][cc] = y[q][cc];
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) cur[q][rb] = mfma(uf[ks], lf[q][rb][ks], cur[q][rb]);
+#pragma unroll
+        for (int q = 0; q < RPT; ++q)
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                const int row = g * R + q * kPanelThreads + wave * kWave + rb * 16 + l16;
+                const bool rok = row >= right0 && row < m;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int c = ct * 16 + Acc<T>::col(lg, r);
+                    if (rok && c < ncols) A[row + (long long)(right0 + c) * lda] = cur[q][rb][r];
+                }
+            }
     }
 }
 
@@ -558,15 +569,8 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
                     sh.U[cc][s] = (s < nbw) ? A[(cb + s) + (long long)(right0 + cc) * lda] : T(0);
                 }
                 __syncthreads();
-                int rows[RPT];
-                bool any = false;
-#pragma unroll
-                for (int q = 0; q < RPT; ++q) {
-                    const int i = g * R + q * kPanelThreads + tid;
-                    rows[q] = (i >= right0 && i < m) ? i : -1;
-                    any |= rows[q] >= 0;
-                }
-                if (any) inpanel_update<T, NB, RPT>(A, lda, rows, cb, nbw, right0, ncols, sh.U, sh.fin);
+                // every row of this work-group lies above right0: nothing to update
+                if (g * R + R > right0) inpanel_update<T, NB, RPT>(A, lda, g, m, cb, nbw, right0, ncols, sh.U, sh.fin);
                 __syncthreads();
             }
         }
