@@ -186,6 +186,32 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_half_sub(int M, int N, int K
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = v4f{0.f, 0.f, 0.f, 0.f};
+    // The update is bound by C's traffic: its tile and the scales are loaded
+    // first, so that they arrive while the matrix cores work.
+    v4f cpre[4][4];
+    float rsc[4], csc[4][4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+        const int row = m0 + wm * 64 + rb * 16 + l16;
+        const bool rok = row < M;
+        rsc[rb] = rs[rok ? row : 0];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int col = n0 + wn * 64 + cb * 16 + 4 * lg + r;
+                const bool ok = rok && col < N;
+                const float v = C[(ok ? row : 0) + (long long)(ok ? col : 0) * ldc];
+                cpre[rb][cb][r] = ok ? v : 0.f;
+            }
+    }
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int col = n0 + wn * 64 + cb * 16 + 4 * lg + r;
+            csc[cb][r] = cs[col < N ? col : 0];
+        }
 
     // each thread moves 4 chunks of 8 halves (16 B) for A and for B per k-tile
     const int ld_row = tid / 8 * 1, ld_chunk = tid % 8;      // 32 rows x 8 chunks per pass
@@ -246,16 +272,12 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_half_sub(int M, int N, int K
     for (int rb = 0; rb < 4; ++rb) {
         const int row = m0 + wm * 64 + rb * 16 + l16;
         if (row < M) {
-            const float rsc = rs[row];
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int col = n0 + wn * 64 + cb * 16 + 4 * lg + r;
-                    if (col < N) {
-                        float* p = C + row + (long long)col * ldc;
-                        *p = *p - (acc[rb][cb][r] * rsc) * cs[col];
-                    }
+                    if (col < N) C[row + (long long)col * ldc] = cpre[rb][cb][r] - (acc[rb][cb][r] * rsc[rb]) * csc[cb][r];
                 }
             }
         }
