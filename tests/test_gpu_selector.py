@@ -121,3 +121,25 @@ def test_selector_range_and_fallback(fresh):
     assert rc == 1 and s == (256, 1, 16)
     rc, s = gpu.lu_selector_predict(6000, 0)
     assert rc == 0 and s[0] in (64, 128, 256, 512) and s[1] in (0, 1, 2) and s[2] in (8, 16, 32)
+
+
+def test_library_inference_matches_oracle_on_committed_weights(fresh):
+    """The weights shipped next to the library: the GPU forward kernel picks the
+    schedule the FP64 oracle of the network picks, at every swept size."""
+    import os
+    from tests.test_selector_regret import PKG, choose, load_weights, sweep
+    gpu = fresh
+    theta, _, _ = load_weights()
+    assert gpu.lu_selector_load(os.path.join(PKG, "selector_weights.bin")) == 0
+    d, _ = sweep()
+    from paper_1804_07017_amd import tune
+    checked = 0
+    for n in d["train_sizes"] + d["heldout_sizes"]:
+        for prec in (0, 1, 2):
+            z = mlp.forward(theta, np.array([tune.features(n, prec)]))[2][0]
+            if min(np.sort(z[lo:hi])[-1] - np.sort(z[lo:hi])[-2] for lo, hi in mlp.HEADS) < 1e-4:
+                continue
+            rc, s = gpu.lu_selector_predict(n, prec)
+            assert rc == 0 and s == choose(theta, n, prec), (n, prec, s)
+            checked += 1
+    assert checked >= 30
