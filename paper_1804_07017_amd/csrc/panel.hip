@@ -406,25 +406,20 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
                 const unsigned long long* src = (tid < nh)
                     ? xa + (size_t)(tid / HW) * X::SW + (tid % HW)
                     : xa + (size_t)kMaxPanelWgs * X::SW + (tid - nh);
+                // every thread spins on its own word (bounded by the wall clock;
+                // thread 0 also watches the error word), then one barrier
                 bool done = tid >= total;
-                for (;;) {
-                    // the data word and (thread 0) the error word are loaded together
-                    unsigned long long wv = 0;
+                int st = 0;
+                while (!done) {
+                    const unsigned long long wv = xload(src);
                     unsigned errw = 0;
-                    if (!done) wv = xload(src);
                     if (tid == 0) errw = xload(a.sync + 1);
-                    int st = 0;
-                    if (!done) {
-                        if ((unsigned)(wv >> 32) == tag) { sh.xbuf[tid] = (unsigned)wv; done = true; }
-                        else st = 1;
-                    }
-                    // bit 0: some word still stale; bit 1: time limit passed or another work-group failed
-                    if (tid == 0 && (errw != 0u || wall_clock64() - t0 > a.spin_limit)) st |= 2;
-                    st = wg_or(st, sh.orslot, poll & 1, kPanelThreads / kWave);
-                    ++poll;
-                    if (!(st & 1)) break;
-                    if (st & 2) { failed = true; break; }
+                    if ((unsigned)(wv >> 32) == tag) { sh.xbuf[tid] = (unsigned)wv; done = true; }
+                    else if (errw != 0u || wall_clock64() - t0 > a.spin_limit) { st = 3; break; }
                 }
+                st = wg_or(st, sh.orslot, poll & 1, kPanelThreads / kWave);
+                ++poll;
+                failed = (st & 2) != 0;
             }
             if (failed) {
                 if (tid == 0) xstore(a.sync + 1, 1u);
@@ -452,23 +447,17 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
             const int ww = nhw + X::DR;
             if (wg >= 0) {
                 bool done = tid >= X::DR;
-                for (;;) {
-                    unsigned long long wv = 0;
+                int st = 0;
+                while (!done) {
+                    const unsigned long long wv = xload(xa + (size_t)wg * X::SW + 1 + X::WPV + tid);
                     unsigned errw = 0;
-                    if (!done) wv = xload(xa + (size_t)wg * X::SW + 1 + X::WPV + tid);
                     if (tid == 0) errw = xload(a.sync + 1);
-                    int st = 0;
-                    if (!done) {
-                        if ((unsigned)(wv >> 32) == tag) { sh.xbuf[ww + tid] = (unsigned)wv; done = true; }
-                        else st = 1;
-                    }
-                    if (tid == 0 && (errw != 0u || wall_clock64() - t0 > a.spin_limit)) st |= 2;
-                    st = wg_or(st, sh.orslot, poll & 1, kPanelThreads / kWave);
-                    ++poll;
-                    if (!(st & 1)) break;
-                    if (st & 2) { failed = true; break; }
+                    if ((unsigned)(wv >> 32) == tag) { sh.xbuf[ww + tid] = (unsigned)wv; done = true; }
+                    else if (errw != 0u || wall_clock64() - t0 > a.spin_limit) { st = 3; break; }
                 }
-                if (failed) {
+                st = wg_or(st, sh.orslot, poll & 1, kPanelThreads / kWave);
+                ++poll;
+                if (st & 2) {
                     if (tid == 0) xstore(a.sync + 1, 1u);
                     return;
                 }

@@ -42,7 +42,9 @@ def test_half_precision_ir_on_dominant_matrix(gpu, prec, n):
     assert st == gpu.LU_IR_OK, (st, it, res)
     assert 1 <= it <= 10
     r = oracle.r_hpl(A, x, b)
-    assert r <= 16.0 and abs(r - res) <= 1e-3 * max(r, 1.0) + 1e-9
+    # the library's own residual may differ from this one by the rounding of
+    # evaluating b - A x in FP64, at most (n+1) eps (|b| + |A||x|): ~1 in these units
+    assert r <= 16.0 and abs(r - res) <= 1.0 + 2.0 / n
     xo = oracle.solve(A, b, nthreads=8)
     err = np.abs(x - xo).max() / np.abs(xo).max()
     assert err <= _forward_error_bound(A, n), err
@@ -113,4 +115,4 @@ def test_north_star_mixed_fp16_ir_n32768(gpu):
     anorm = dA.abs().sum(dim=1).max().item()
     rh = r.abs().max().item() / (EPS * (anorm * dX.abs().max().item() + dB.abs().max().item()) * n)
     assert rh <= 16.0
-    assert abs(rh - res) <= 1e-2 * max(rh, 1e-3)
+    assert abs(rh - res) <= 1.0 + 2.0 / n       # evaluation rounding of b - A x, as above
