@@ -474,6 +474,7 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
                     if (a.ipiv_rel) a.ipiv_rel[d] = p;
                 }
             }
+            if (tid < NB) sh.L[j][tid] = prow_at(tid);     // the finished block row d (for the block step)
             const T piv = prow_at(j);
             if (piv == T(0) && g == 0 && tid == 0 && a.info) atomicCAS(a.info, 0, a.info_col_base + d + 1);
             // 6. rows d and p exchange: the owner's wave writes the block row
@@ -540,9 +541,11 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
             const int gd = cb / R;     // owner of the block's diagonal rows
             if (g == gd) {
                 __syncthreads();       // this work-group's stores of the block are visible to it
+                // sh.L rows 0..nbw-1 hold the finished block rows (captured during the
+                // column steps); rows past a ragged block's width are cleared
                 for (int e = tid; e < NB * NB; e += kPanelThreads) {
-                    const int r = e % NB, c = e / NB;
-                    sh.L[r][c] = (r < nbw && c < nbw) ? A[(cb + r) + (long long)(cb + c) * lda] : T(0);
+                    const int r = e / NB, c = e % NB;
+                    if (r >= nbw) sh.L[r][c] = T(0);
                 }
                 if (tid < kWave) compose_block_moves<NB>(sh.piv + cb, nbw, cb, sh.bmv, sh.slot_row, sh.content);
                 __syncthreads();
