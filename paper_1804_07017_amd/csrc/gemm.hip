@@ -29,14 +29,21 @@ constexpr int kBM = 128, kBN = 128, kThreads = 256;
 
 // Map the linear work-group id to a (tile_m, tile_n) pair.  Work-groups are
 // dealt to the 8 XCDs round-robin; this remap gives each XCD a contiguous
-// band of tile columns so that its L2 keeps reusing the same B columns.
+// chunk of the tile order, and the order walks kGroupM tile-rows down before
+// moving to the next tile column, so that the A rows and B columns of the
+// tiles an XCD runs at the same time stay in its L2.
+constexpr int kGroupM = 8;
 __device__ __forceinline__ void tile_of(int tiles_m, int tiles_n, int& tm, int& tn) {
     const int nt = tiles_m * tiles_n;
     int bid = blockIdx.x;
     const int per = nt / 8;
     if (per > 0 && bid < per * 8) bid = (bid % 8) * per + bid / 8;
-    tm = bid % tiles_m;
-    tn = bid / tiles_m;
+    const int grp = kGroupM * tiles_n;
+    const int gi = bid / grp, r = bid % grp;
+    const int m0 = gi * kGroupM;
+    const int gh = min(kGroupM, tiles_m - m0);
+    tm = m0 + r % gh;
+    tn = r / gh;
 }
 
 template <typename T, int BK>
