@@ -136,12 +136,14 @@ void release_all() {
     g_states.clear();
 }
 
-int panel_wgs_for(const DeviceState& s, int m, int panel_cus) {
+int panel_wgs_for(const DeviceState& s, int m, int panel_cus, bool wide) {
     // Rows per work-group: up to 2*threads (the register-resident variants),
-    // 4*threads only when even kPanelMaxWgs groups would not cover m that way.
+    // 4*threads when even kPanelMaxWgs groups would not cover m that way, or
+    // when `wide` asks for fewer, fuller groups (a tall FP64 panel that runs
+    // beside a long trailing update: its CUs are worth more to the update).
     const int t = panel_threads();
     int need = (m + 2 * t - 1) / (2 * t);
-    if (need > kPanelMaxWgs) need = (m + panel_max_rows_per_wg() - 1) / panel_max_rows_per_wg();
+    if (need > kPanelMaxWgs || wide) need = (m + panel_max_rows_per_wg() - 1) / panel_max_rows_per_wg();
     // no more groups than rows / threads: fewer, fuller groups make cheaper barriers
     const int useful = std::max(need, (m + t - 1) / t);
     const int wgs = std::min(std::max(need, std::max(1, panel_cus)), useful);
@@ -193,6 +195,8 @@ const std::vector<PlanTask>* get_plan(DeviceState* s, int n, int b, int depth) {
 // ---------------------------------------------------------------- executor
 struct HalfNone {};
 
+constexpr int kWidePanelRows = 20480;
+
 template <typename T>
 int run_panel(DeviceState* s, T* A, long long lda, int n, int j0, int w, int* ipiv, int* info, int* moves,
               int wgs_req, hipStream_t st) {
@@ -222,7 +226,9 @@ int run_panel(DeviceState* s, T* A, long long lda, int n, int j0, int w, int* ip
     pa.tag_base = (unsigned)s->panel_launches << 10;
     pa.spin_limit = s->spin_limit;
     pa.occupancy = s->panel_occupancy;
-    int wgs = panel_wgs_for(*s, m, wgs_req);
+    // tall FP64 panels (m > kWidePanelRows) use 4*threads rows per group
+    const bool wide = sizeof(T) == 8 && m > kWidePanelRows;
+    int wgs = panel_wgs_for(*s, m, wgs_req, wide);
     if (wgs < 0) return LU_ERR_UNSUPPORTED;
     return launch_panel<T>(pa, wgs, st) == 0 ? 0 : LU_ERR_HIP;
 }

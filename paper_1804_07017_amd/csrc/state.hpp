@@ -56,6 +56,6 @@ struct DeviceState {
 
 DeviceState* device_state(int* err);
 void release_all();
-int panel_wgs_for(const DeviceState& s, int m, int panel_cus);
+int panel_wgs_for(const DeviceState& s, int m, int panel_cus, bool wide = false);
 
 }  // namespace lu
