@@ -64,6 +64,11 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_nn_sub(int M, int N, int K, 
     const int l16 = lane % 16, lg = lane / 16;
     const int wm = wave % 2, wn = wave / 2;
 
+    // Tiles inside the matrix (all but the last tile row and column) take a
+    // branch-free path: no per-element bounds checks, B read two k at a time.
+    const bool interior = m0 + kBM <= M && n0 + kBN <= N;
+    const bool vecb = interior && (reinterpret_cast<unsigned long long>(B) % (2 * sizeof(T))) == 0 && (ldb % 2) == 0;
+
     // accumulators start from C
     V4 acc[4][4];
 #pragma unroll
@@ -74,7 +79,8 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_nn_sub(int M, int N, int K, 
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int col = n0 + wn * 64 + cb * 16 + Acc<T>::col(lg, r);
-                acc[rb][cb][r] = (row < M && col < N) ? C[row + (long long)col * ldc] : T(0);
+                if (interior) acc[rb][cb][r] = C[row + (long long)col * ldc];
+                else acc[rb][cb][r] = (row < M && col < N) ? C[row + (long long)col * ldc] : T(0);
             }
         }
     }
@@ -88,7 +94,26 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_nn_sub(int M, int N, int K, 
     const int b_col = tid / (kThreads / kBN), b_kh = tid % (kThreads / kBN);   // B: k contiguous
     constexpr int BKS = BK / (kThreads / kBN);
 
+    static_assert(BKS % 2 == 0, "B is read two k at a time");
+    typedef T T2 __attribute__((ext_vector_type(2)));
     auto load = [&](int k0) {
+        if (interior && k0 + BK <= K) {
+#pragma unroll
+            for (int r = 0; r < AL; ++r) ra[r] = A[m0 + a_row + (long long)(k0 + a_k0 + AKS * r) * lda];
+            const T* bp = B + k0 + b_kh * BKS + (long long)(n0 + b_col) * ldb;
+            if (vecb) {
+#pragma unroll
+                for (int e = 0; e < BL; e += 2) {
+                    const T2 v = *reinterpret_cast<const T2*>(bp + e);
+                    rbv[e] = v.x;
+                    rbv[e + 1] = v.y;
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < BL; ++e) rbv[e] = bp[e];
+            }
+            return;
+        }
 #pragma unroll
         for (int r = 0; r < AL; ++r) {
             const int kk = a_k0 + AKS * r;
@@ -135,13 +160,13 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_nn_sub(int M, int N, int K, 
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
         const int row = m0 + wm * 64 + rb * 16 + l16;
-        if (row < M) {
+        if (interior || row < M) {
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int col = n0 + wn * 64 + cb * 16 + Acc<T>::col(lg, r);
-                    if (col < N) C[row + (long long)col * ldc] = acc[rb][cb][r];
+                    if (interior || col < N) C[row + (long long)col * ldc] = acc[rb][cb][r];
                 }
             }
         }
