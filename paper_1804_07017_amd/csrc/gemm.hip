@@ -248,7 +248,22 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_half_sub(int M, int N, int K
     // each thread moves 4 chunks of 8 halves (16 B) for A and for B per k-tile
     const int ld_row = tid / 8 * 1, ld_chunk = tid % 8;      // 32 rows x 8 chunks per pass
     VH ra[4], rb4[4];
+    // tiles inside the matrix take a branch-free path (16-byte loads need the
+    // k offsets and leading dimensions to be multiples of 8 halves)
+    const bool interior = m0 + kBM <= M && n0 + kBN <= N && lda_h % 8 == 0 && ldb_h % 8 == 0 &&
+                          (reinterpret_cast<unsigned long long>(Ah) % 16) == 0 &&
+                          (reinterpret_cast<unsigned long long>(Bh) % 16) == 0;
     auto load = [&](int k0) {
+        if (interior && k0 + BK <= K) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const int row = ld_row + 32 * p;
+                const int gk = k0 + ld_chunk * 8;
+                ra[p] = *reinterpret_cast<const VH*>(Ah + (long long)(m0 + row) * lda_h + gk);
+                rb4[p] = *reinterpret_cast<const VH*>(Bh + (long long)(n0 + row) * ldb_h + gk);
+            }
+            return;
+        }
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
             const int row = ld_row + 32 * p;
