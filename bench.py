@@ -25,6 +25,38 @@ sys.path.insert(0, ROOT)
 METRIC = "LU GFLOPS (2/3·n³/t) at n=32768, FP64 vs mixed+IR; % MFMA peak; IR time-to-solve"
 FP64_PEAK_TFLOPS = 78.6
 
+# HBM bytes per launch of the FP64 trailing GEMM, from two rocprofv3 --pmc passes
+# (FETCH_SIZE, then WRITE_SIZE) over one bench step, each scaled by what the same
+# counter reads for the bench's own n*n*8-byte device copy (see
+# profiles/gemm_f64_n32768_hbm_traffic.md).  Valid only for the schedule and the
+# GEMM source it was measured with; otherwise the bench reports null.
+GEMM_TRAFFIC = {"n": 32768, "b": 256, "depth": 2, "gemm_source_sha256_16": "da481556bd8b455d",
+                "bytes_per_launch": 2691415394}
+
+
+def gemm_source_hash():
+    import hashlib
+    path = os.path.join(ROOT, "paper_1804_07017_amd", "csrc", "gemm.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def gemm_algorithmic_bytes(lu, n, b, depth):
+    """Mean per-launch bytes the trailing GEMMs of one factorization must move:
+    C read and written once, A21 and U12 read once (8-byte elements)."""
+    rc, tasks = lu.lu_plan_build(n, b, depth)
+    tot, cnt = 0.0, 0
+    for t in tasks:
+        if t["kind"] != lu.LU_TASK_UPDATE:
+            continue
+        kb = t["step"] * b
+        wk = min(b, n - kb)
+        m, w = n - kb - wk, t["col_end"] - t["col_begin"]
+        if m > 0 and w > 0:
+            tot += 16.0 * m * w + 8.0 * m * wk + 8.0 * wk * w
+            cnt += 1
+    return tot / max(cnt, 1)
+
 
 def cpu_baseline(budget_s=20.0):
     """Time the CPU oracle on a bounded sample of the same workload: one
@@ -181,9 +213,15 @@ def main():
                            "effective_gflops": round(flops / (t_ir * 1e-3) / 1e9, 1)}
     if rc_t == 0 and gemm_launches > 0:
         ach = gemm_flops / (gemm_ms * 1e-3) / 1e12
+        traffic = None
+        if (GEMM_TRAFFIC["n"], GEMM_TRAFFIC["b"], GEMM_TRAFFIC["depth"]) == (n, used[0], used[1]) and \
+                GEMM_TRAFFIC["gemm_source_sha256_16"] == gemm_source_hash():
+            traffic = GEMM_TRAFFIC["bytes_per_launch"]
         out["roofline"] = {"bound": "mfma", "kernel": "gemm_nn_sub<double,16> (trailing update)",
                            "achieved": round(ach, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                           "frac": round(ach / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                           "frac": round(ach / FP64_PEAK_TFLOPS, 4), "traffic": traffic,
+                           "traffic_unit": "bytes per launch",
+                           "algorithmic_bytes_per_launch": round(gemm_algorithmic_bytes(lu, n, used[0], used[1])),
                            "launches": gemm_launches,
                            "avg_launch_us": round(gemm_ms * 1e3 / gemm_launches, 2),
                            "avg_launch_gflop": round(gemm_flops / gemm_launches / 1e9, 3)}
