@@ -105,17 +105,23 @@ struct PanelShared {
 //   L(t) = last t' != t with q[t'] == t;  f(t) = f(L(t)) or t;
 //   prev(t) = last t' < t with q[t'] == q[t];
 //   top t <- f(t) if q[t]==t, else f(prev(t)) or q[t];  extra e <- f(last t with q[t]==e).
-// bmv: [0] count, then (dst, src) pairs as panel rows.  lt / ft: LDS scratch.
+// bmv: [0] number of extra moves, then their (dst, src) pairs as panel rows;
+// bmv[1 + 2 NB + t] = source row of top row t (t < nbw).  lt / ft: LDS scratch.
 template <int NB>
 __device__ __forceinline__ void compose_block_moves(const int* piv, int nbw, int t0, int* bmv, int* lt, int* ft) {
     const int lane = threadIdx.x & (kWave - 1);
     const int q = lane < nbw ? piv[lane] - t0 : -1;
-    if (lane < nbw) {
-        int L = -1;
-        for (int u = 0; u < nbw; ++u)
-            if (u != lane && piv[u] - t0 == lane) L = u;
-        lt[lane] = L;
+    int Lx = -1, prv = -1;
+    bool last = true;
+    for (int u = 0; u < nbw; ++u) {            // q of lane u, broadcast from its register
+        const int qu = __builtin_amdgcn_readlane(q, u);
+        if (u != lane && qu == lane) Lx = u;
+        if (qu == q) {
+            if (u < lane) prv = u;
+            if (u > lane) last = false;
+        }
     }
+    if (lane < nbw) lt[lane] = Lx;
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     if (lane < nbw) {
@@ -125,81 +131,66 @@ __device__ __forceinline__ void compose_block_moves(const int* piv, int nbw, int
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    int top_src = -1, ex_dst = -1, ex_src = -1;
+    int ex_dst = -1, ex_src = -1;
     if (lane < nbw) {
-        int prv = -1;
-        bool last = true;
-        for (int u = 0; u < nbw; ++u) {
-            const int qu = piv[u] - t0;
-            if (qu == q) {
-                if (u < lane) prv = u;
-                if (u > lane) last = false;
-            }
-        }
-        top_src = (q == lane) ? ft[lane] : (prv >= 0 ? ft[prv] : q);
+        const int top_src = (q == lane) ? ft[lane] : (prv >= 0 ? ft[prv] : q);
+        bmv[1 + 2 * NB + lane] = t0 + top_src;
         if (q >= nbw && last) { ex_dst = q; ex_src = ft[lane]; }
     }
-    // pack the changed moves: lane order, top moves then extra moves
-    const bool has_top = lane < nbw && top_src != lane;
+    // pack the extra moves in lane order
     const bool has_ex = ex_dst >= 0;
-    const unsigned long long mt = __ballot(has_top), me = __ballot(has_ex);
-    const int nt = __popcll(mt);
+    const unsigned long long me = __ballot(has_ex);
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    if (has_top) {
-        const int slot = __popcll(mt & below);
-        bmv[1 + 2 * slot] = t0 + lane;
-        bmv[2 + 2 * slot] = t0 + top_src;
-    }
     if (has_ex) {
-        const int slot = nt + __popcll(me & below);
+        const int slot = __popcll(me & below);
         bmv[1 + 2 * slot] = t0 + ex_dst;
         bmv[2 + 2 * slot] = t0 + ex_src;
     }
-    if (lane == 0) bmv[0] = nt + __popcll(me);
+    if (lane == 0) bmv[0] = __popcll(me);
 }
 
 // Interchanges of one block on the other panel columns and, on the columns to
 // its right, the unit-lower NB x NB solve for the block's U rows.  One thread
-// per column.
+// per column; work-group g of P takes columns t*P + g (thread t), so every CU
+// of the panel shares the strided row accesses.  Each thread loads the block's
+// top rows from their sources and the extra rows' sources before it stores
+// anything, so the column's moves read only old values.
 template <typename T, int NB>
-__device__ __forceinline__ void block_swap_trsm(T* A, long long lda, int w, int cb, int nbw,
+__device__ __forceinline__ void block_swap_trsm(T* A, long long lda, int w, int cb, int nbw, int g, int P,
                                                 const int* bmv, const T (*L)[NB + 1]) {
-    // Indices are clamped instead of guarded: every load and store is
-    // unconditional (surplus lanes repeat the last move / row with its own
-    // value), which keeps the code free of per-element branches.
-    const int cnt = bmv[0];
-    const int cm1 = cnt > 0 ? cnt - 1 : 0;
-    for (int c = threadIdx.x; c < w - nbw; c += kPanelThreads) {
+    // source indices are clamped to written entries, so no load can use an
+    // unset one; the count is the same for every thread (scalar branches)
+    const int ne = __builtin_amdgcn_readfirstlane(bmv[0]);
+    const int em1 = ne > 0 ? ne - 1 : 0;
+    const int* tsrc = bmv + 1 + 2 * NB;
+    for (int c = threadIdx.x * P + g; c < w - nbw; c += kPanelThreads * P) {
         const int col = (c < cb) ? c : c + nbw;
         T* colp = A + (long long)col * lda;
-        if (cnt > 0) {
-            T v[2 * NB];
+        T x[NB], e[NB];
 #pragma unroll
-            for (int s = 0; s < 2 * NB; ++s) v[s] = colp[bmv[2 + 2 * min(s, cm1)]];
+        for (int r = 0; r < NB; ++r) {
+            const T v = colp[tsrc[min(r, nbw - 1)]];
+            x[r] = (r < nbw) ? v : T(0);
+        }
 #pragma unroll
-            for (int s = 0; s < 2 * NB; ++s) colp[bmv[1 + 2 * min(s, cm1)]] = v[s];   // v[s] == v[cm1] for s > cm1
+        for (int s = 0; s < NB; ++s) {
+            e[s] = T(0);
+            if (s < ne) e[s] = colp[bmv[2 + 2 * min(s, em1)]];
         }
         if (col >= cb + nbw) {
             const T* Lf = &L[0][0];
-            T x[NB];
-#pragma unroll
-            for (int r = 0; r < NB; ++r) {
-                const T v = colp[cb + min(r, nbw - 1)];
-                x[r] = (r < nbw) ? v : T(0);
-            }
 #pragma unroll
             for (int s = 0; s < NB; ++s) {
 #pragma unroll
                 for (int r = s + 1; r < NB; ++r) x[r] = x[r] - Lf[r * (NB + 1) + s] * x[s];
             }
-#pragma unroll
-            for (int r = 0; r < NB; ++r) {
-                T xr = x[0];
-#pragma unroll
-                for (int k = 1; k < NB; ++k) xr = (min(r, nbw - 1) == k) ? x[k] : xr;
-                colp[cb + min(r, nbw - 1)] = xr;
-            }
         }
+#pragma unroll
+        for (int r = 0; r < NB; ++r)
+            if (r < nbw) colp[cb + r] = x[r];
+#pragma unroll
+        for (int s = 0; s < NB; ++s)
+            if (s < ne) colp[bmv[1 + 2 * min(s, em1)]] = e[s];
     }
 }
 
@@ -538,19 +529,23 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
 
         const bool more_cols = (w - cb - nbw) > 0 || cb > 0;
         if (more_cols) {
-            const int gd = cb / R;     // owner of the block's diagonal rows
-            if (g == gd) {
-                __syncthreads();       // this work-group's stores of the block are visible to it
-                // sh.L rows 0..nbw-1 hold the finished block rows (captured during the
-                // column steps); rows past a ragged block's width are cleared
+            // every work-group: the block's moves (from its own copy of the
+            // pivots) and its share of the columns
+            __syncthreads();           // the last step's pivot and block row are in LDS
+            // every work-group's rows as its last in-panel update left them (that
+            // update preceded its exchange words, which this work-group has read)
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            // sh.L rows 0..nbw-1 hold the finished block rows (captured during the
+            // column steps); rows past a ragged block's width are cleared
+            if (nbw < NB) {
                 for (int e = tid; e < NB * NB; e += kPanelThreads) {
                     const int r = e / NB, c = e % NB;
                     if (r >= nbw) sh.L[r][c] = T(0);
                 }
-                if (tid < kWave) compose_block_moves<NB>(sh.piv + cb, nbw, cb, sh.bmv, sh.slot_row, sh.content);
-                __syncthreads();
-                block_swap_trsm<T, NB>(A, lda, w, cb, nbw, sh.bmv, sh.L);
             }
+            if (tid < kWave) compose_block_moves<NB>(sh.piv + cb, nbw, cb, sh.bmv, sh.slot_row, sh.content);
+            __syncthreads();
+            block_swap_trsm<T, NB>(A, lda, w, cb, nbw, g, P, sh.bmv, sh.L);
             if (grid_barrier(a.sync, a.sync + 1, ++epoch, a.spin_limit)) return;
             // in-panel trailing update of my rows below the block: A[i, right] -= L[i, blk] U[blk, right]
             const int right0 = cb + nbw;
@@ -564,6 +559,9 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
                 // every row of this work-group lies above right0: nothing to update
                 if (g * R + R > right0) inpanel_update<T, NB, RPT>(A, lda, g, m, cb, nbw, right0, ncols, sh.U, sh.fin);
                 __syncthreads();
+                // the next block step of other work-groups reads these rows: publish
+                // them before this work-group's first exchange word of the next block
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             }
         }
     }
