@@ -30,7 +30,7 @@ FP64_PEAK_TFLOPS = 78.6
 # counter reads for the bench's own n*n*8-byte device copy (see
 # profiles/gemm_f64_n32768_hbm_traffic.md).  Valid only for the schedule and the
 # GEMM source it was measured with; otherwise the bench reports null.
-GEMM_TRAFFIC = {"n": 32768, "b": 256, "depth": 2, "gemm_source_sha256_16": "da481556bd8b455d",
+GEMM_TRAFFIC = {"n": 32768, "b": 256, "depth": 2, "taper": 0, "gemm_source_sha256_16": "da481556bd8b455d",
                 "bytes_per_launch": 2691415394}
 
 
@@ -41,16 +41,17 @@ def gemm_source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def gemm_algorithmic_bytes(lu, n, b, depth):
+def gemm_algorithmic_bytes(lu, n, b, depth, taper):
     """Mean per-launch bytes the trailing GEMMs of one factorization must move:
     C read and written once, A21 and U12 read once (8-byte elements)."""
-    rc, tasks = lu.lu_plan_build(n, b, depth)
+    rc, starts = lu.lu_plan_panels(n, b, taper, lu.LU_FP64)
+    rc, tasks = lu.lu_plan_build_panels(n, starts, depth)
     tot, cnt = 0.0, 0
     for t in tasks:
         if t["kind"] != lu.LU_TASK_UPDATE:
             continue
-        kb = t["step"] * b
-        wk = min(b, n - kb)
+        kb = starts[t["step"]]
+        wk = starts[t["step"] + 1] - kb
         m, w = n - kb - wk, t["col_end"] - t["col_begin"]
         if m > 0 and w > 0:
             tot += 16.0 * m * w + 8.0 * m * wk + 8.0 * wk * w
@@ -88,6 +89,7 @@ def main():
     ap.add_argument("--b", type=int, default=0)
     ap.add_argument("--depth", type=int, default=-1)
     ap.add_argument("--panel-cus", type=int, default=0)
+    ap.add_argument("--taper", type=int, default=0, help="panel taper: 1 on, -1 off, 0 library default")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ir", action="store_true")
     args = ap.parse_args()
@@ -121,11 +123,13 @@ def main():
         X = torch.empty(n, dtype=torch.float64, device=dev)
     stream = torch.cuda.Stream()
     sched = None
-    if args.b > 0 or args.depth >= 0 or args.panel_cus > 0:
-        sched = (args.b, args.depth if args.depth >= 0 else 1, args.panel_cus)
+    if args.b > 0 or args.depth >= 0 or args.panel_cus > 0 or args.taper != 0:
+        rc, dflt = lu.lu_schedule_default(n, lu.LU_FP64)
+        sched = (args.b, args.depth if args.depth >= 0 else dflt[1], args.panel_cus, args.taper)
     rc, used = lu.lu_schedule_default(n, lu.LU_FP64)
     if sched is not None:
-        used = (sched[0] or used[0], sched[1], sched[2] or used[2])
+        used = (sched[0] or used[0], sched[1], sched[2] or used[2], sched[3] or used[3])
+    taper_on = 1 if used[3] > 0 else 0
     torch.cuda.synchronize()
 
     def step(rec):
@@ -199,7 +203,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "FP64 look-ahead LU + 1-RHS solve of a uniform[-1,1) n=%d matrix; mixed FP16 LU "
                                "+ FP64 refinement on the row-dominant n=%d matrix" % (n, n),
-                   "n": n, "b": used[0], "depth": used[1], "panel_cus": used[2]},
+                   "n": n, "b": used[0], "depth": used[1], "panel_cus": used[2], "taper": taper_on},
         "fp64": {"t_factor_ms": round(t_fact, 3), "t_solve_ms": round(t_solve, 3),
                  "tts_ms": round(t_fact + t_solve, 3), "pct_fp64_peak": round(100 * gflops / 1e3 / FP64_PEAK_TFLOPS, 2),
                  "hpl_resid": hpl},
@@ -214,14 +218,16 @@ def main():
     if rc_t == 0 and gemm_launches > 0:
         ach = gemm_flops / (gemm_ms * 1e-3) / 1e12
         traffic = None
-        if (GEMM_TRAFFIC["n"], GEMM_TRAFFIC["b"], GEMM_TRAFFIC["depth"]) == (n, used[0], used[1]) and \
+        if (GEMM_TRAFFIC["n"], GEMM_TRAFFIC["b"], GEMM_TRAFFIC["depth"], GEMM_TRAFFIC["taper"]) == \
+                (n, used[0], used[1], taper_on) and \
                 GEMM_TRAFFIC["gemm_source_sha256_16"] == gemm_source_hash():
             traffic = GEMM_TRAFFIC["bytes_per_launch"]
         out["roofline"] = {"bound": "mfma", "kernel": "gemm_nn_sub<double,16> (trailing update)",
                            "achieved": round(ach, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                            "frac": round(ach / FP64_PEAK_TFLOPS, 4), "traffic": traffic,
                            "traffic_unit": "bytes per launch",
-                           "algorithmic_bytes_per_launch": round(gemm_algorithmic_bytes(lu, n, used[0], used[1])),
+                           "algorithmic_bytes_per_launch": round(gemm_algorithmic_bytes(lu, n, used[0], used[1],
+                                                                                        taper_on)),
                            "launches": gemm_launches,
                            "avg_launch_us": round(gemm_ms * 1e3 / gemm_launches, 2),
                            "avg_launch_gflop": round(gemm_flops / gemm_launches / 1e9, 3)}

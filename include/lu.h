@@ -54,12 +54,17 @@ typedef enum {
 
 /* Schedule: algorithmic block size b, look-ahead depth (0 = none, the
  * conventional loop; 1 = the paper's one-panel look-ahead; 2 = two panels),
- * and the number of compute units given to the panel work.  A field <= 0
- * means "choose" (explicit value > environment > selector > default). */
+ * the number of compute units given to the panel work, and the panel taper
+ * (early termination done statically, Sec. 4.2: 1 = panels narrow to 128
+ * columns once the trailing matrix is small, see lu_plan_panels in
+ * lu_plan.h; -1 = every panel b wide).  A field 0 (b, panel_cus, taper) or
+ * < 0 (b, depth, panel_cus) means "choose" (explicit value > environment >
+ * selector > default; the taper's default is on). */
 typedef struct {
     int b;
     int depth;
     int panel_cus;
+    int taper;
 } lu_schedule_t;
 
 #define LU_ERR_HIP         (-100)  /* a HIP runtime call failed                           */

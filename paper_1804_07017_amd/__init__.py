@@ -28,7 +28,8 @@ _lib = None
 
 
 class Schedule(ctypes.Structure):
-    _fields_ = [("b", ctypes.c_int), ("depth", ctypes.c_int), ("panel_cus", ctypes.c_int)]
+    _fields_ = [("b", ctypes.c_int), ("depth", ctypes.c_int), ("panel_cus", ctypes.c_int),
+                ("taper", ctypes.c_int)]
 
 
 class PlanTask(ctypes.Structure):
@@ -57,6 +58,8 @@ _SIGS = {
     "lu_selector_grad": (_I, [_P, _P, _I, _P, _P]),
     "lu_release": (None, []),
     "lu_plan_build": (_I, [_I, _I, _I, ctypes.POINTER(PlanTask), _I]),
+    "lu_plan_panels": (_I, [_I, _I, _I, _I, ctypes.POINTER(_I), _I]),
+    "lu_plan_build_panels": (_I, [_I, ctypes.POINTER(_I), _I, _I, ctypes.POINTER(PlanTask), _I]),
     "lu_k_panel": (_I, [_I, _I, _I, _P, _I, _P, _I, _P, _P]),
     "lu_k_update": (_I, [_I, _I, _I, _I, _P, _I, _P, _P, _I, _P]),
     "lu_k_gemm": (_I, [_I, _I, _I, _I, _P, _I, _P, _I, _P, _I, _P]),
@@ -150,8 +153,9 @@ def _sched(sched):
         return None
     if isinstance(sched, Schedule):
         return ctypes.byref(sched)
-    b, d, p = sched
-    return ctypes.byref(Schedule(int(b), int(d), int(p)))
+    b, d, p = sched[:3]
+    taper = sched[3] if len(sched) > 3 else 0
+    return ctypes.byref(Schedule(int(b), int(d), int(p), int(taper)))
 
 
 # ------------------------------------------------------------------ C ABI
@@ -175,7 +179,7 @@ def lu_factor_info():
 def lu_schedule_default(n, prec=LU_FP64):
     s = Schedule()
     rc = load().lu_schedule_default(int(n), int(prec), ctypes.byref(s))
-    return rc, (s.b, s.depth, s.panel_cus)
+    return rc, (s.b, s.depth, s.panel_cus, s.taper)
 
 
 def lu_solve(LU, ipiv, B):
@@ -254,6 +258,14 @@ def lu_release():
     load().lu_release()
 
 
+def _tasks(arr, rc):
+    out = []
+    for t in arr[:rc]:
+        out.append(dict(kind=t.kind, step=t.step, col_begin=t.col_begin, col_end=t.col_end,
+                        stream=t.stream, waits=[t.wait[i] for i in range(t.nwait)], record=t.record))
+    return out
+
+
 def lu_plan_build(n, b, depth, max_tasks=None):
     """Task list of the look-ahead schedule (host only). Returns (rc, list of dicts)."""
     if max_tasks is None:
@@ -263,11 +275,31 @@ def lu_plan_build(n, b, depth, max_tasks=None):
     rc = load().lu_plan_build(int(n), int(b), int(depth), arr, int(max_tasks))
     if rc < 0:
         return rc, []
-    out = []
-    for t in arr[:rc]:
-        out.append(dict(kind=t.kind, step=t.step, col_begin=t.col_begin, col_end=t.col_end,
-                        stream=t.stream, waits=[t.wait[i] for i in range(t.nwait)], record=t.record))
-    return rc, out
+    return rc, _tasks(arr, rc)
+
+
+def lu_plan_panels(n, b, taper, prec=LU_FP64, max_starts=None):
+    """Panel boundaries [0, ..., n] of a schedule (host only). Returns (rc, list)."""
+    if max_starts is None:
+        max_starts = n + 2
+    arr = (ctypes.c_int * max(1, max_starts))()
+    rc = load().lu_plan_panels(int(n), int(b), int(taper), int(prec), arr, int(max_starts))
+    if rc < 0:
+        return rc, []
+    return rc, list(arr[:rc + 1]) if rc > 0 else []
+
+
+def lu_plan_build_panels(n, starts, depth, max_tasks=None):
+    """Task list for explicit panel boundaries (host only). Returns (rc, list of dicts)."""
+    N = max(0, len(starts) - 1)
+    if max_tasks is None:
+        max_tasks = 8 * N + 16
+    st = (ctypes.c_int * max(1, len(starts)))(*starts)
+    arr = (PlanTask * max(1, max_tasks))()
+    rc = load().lu_plan_build_panels(int(n), st, N, int(depth), arr, int(max_tasks))
+    if rc < 0:
+        return rc, []
+    return rc, _tasks(arr, rc)
 
 
 def lu_k_panel(P, ipiv_rel, prec=LU_FP64, wgs=0, d_info=None, stream=None, m=None, w=None):

@@ -162,15 +162,18 @@ int env_int(const char* name, int dflt) {
     return std::atoi(e);
 }
 
+constexpr int kTaperDefault = 1;   // the early-termination taper is on unless asked otherwise
+
 void resolve_schedule(int n, lu_precision_t prec, const lu_schedule_t* req, lu_schedule_t* out) {
-    lu_schedule_t s = {256, 1, 16};
+    lu_schedule_t s = {256, 1, 16, kTaperDefault};
     lu_schedule_t sel;
     const bool sel_on = selector_enabled() && selector_predict(n, (int)prec, &sel) == 0;
-    if (sel_on) s = sel;
+    if (sel_on) { s.b = sel.b; s.depth = sel.depth; s.panel_cus = sel.panel_cus; }
     int e;
     if ((e = env_int("LU_B", 0)) > 0 && valid_b(e)) s.b = e;
     if ((e = env_int("LU_DEPTH", -1)) >= 0 && e <= 2) s.depth = e;
     if ((e = env_int("LU_PANEL_CUS", 0)) > 0 && e <= 256) s.panel_cus = e;
+    if ((e = env_int("LU_TAPER", 0)) != 0) s.taper = e > 0 ? 1 : -1;
     if (req) {
         if (req->b > 0) s.b = req->b;
         if (req->depth >= 0 && req->depth <= 2 && (req->b > 0 || req->depth > 0 || req->panel_cus > 0)) {
@@ -178,18 +181,24 @@ void resolve_schedule(int n, lu_precision_t prec, const lu_schedule_t* req, lu_s
             s.depth = req->depth;
         }
         if (req->panel_cus > 0) s.panel_cus = req->panel_cus;
+        if (req->taper != 0) s.taper = req->taper > 0 ? 1 : -1;
     }
     *out = s;
 }
 
-const std::vector<PlanTask>* get_plan(DeviceState* s, int n, int b, int depth) {
-    const long long key = ((long long)n << 16) ^ ((long long)b << 4) ^ depth;
+int prec_class(lu_precision_t prec) { return prec == LU_FP64 ? 0 : prec == LU_FP32 ? 1 : 2; }
+
+const DeviceState::Plan* get_plan(DeviceState* s, int n, const lu_schedule_t& sch, lu_precision_t prec) {
+    const int taper = sch.taper > 0 ? 1 : 0;
+    const long long key = ((long long)n << 20) | ((long long)sch.b << 8) | (sch.depth << 4) | (taper << 2) |
+                          prec_class(prec);
     auto it = s->plans.find(key);
     if (it != s->plans.end()) return &it->second;
     if (s->plans.size() > 64) s->plans.clear();
-    std::vector<PlanTask> v;
-    if (build_plan(n, b, depth, v) < 0) return nullptr;
-    return &(s->plans[key] = std::move(v));
+    DeviceState::Plan p;
+    p.starts = panel_starts(n, sch.b, taper, prec_class(prec));
+    if (build_plan(n, p.starts, sch.depth, p.tasks) < 0) return nullptr;
+    return &(s->plans[key] = std::move(p));
 }
 
 // ---------------------------------------------------------------- executor
@@ -235,11 +244,12 @@ int run_panel(DeviceState* s, T* A, long long lda, int n, int j0, int w, int* ip
 
 template <typename T, typename H>
 int execute(DeviceState* s, int n, T* A, long long lda, int* ipiv, int* info, const lu_schedule_t& sch,
-            hipStream_t stream, bool mixed) {
-    const int b = sch.b;
-    const std::vector<PlanTask>* plan = get_plan(s, n, b, sch.depth);
-    if (!plan) return LU_ERR_UNSUPPORTED;
-    const int N = (n + b - 1) / b;
+            lu_precision_t prec, hipStream_t stream, bool mixed) {
+    const DeviceState::Plan* pl = get_plan(s, n, sch, prec);
+    if (!pl) return LU_ERR_UNSUPPORTED;
+    const std::vector<PlanTask>* plan = &pl->tasks;
+    const std::vector<int>& starts = pl->starts;
+    const int N = (int)starts.size() - 1;
     int rc;
     if ((rc = ensure(s->moves, (size_t)N * kMovesLen * sizeof(int)))) return rc;
     int* moves = reinterpret_cast<int*>(s->moves.ptr);
@@ -278,8 +288,8 @@ int execute(DeviceState* s, int n, T* A, long long lda, int* ipiv, int* info, co
             LU_HIP(hipStreamWaitEvent(st, s->events[e], 0));
         }
         const int k = t.step;
-        const int kb = k * b;
-        const int wk = std::min(b, n - kb);
+        const int kb = starts[k];
+        const int wk = starts[k + 1] - kb;
         int* mv = moves + (size_t)k * kMovesLen;
         if (t.kind == kTaskPanel) {
             if ((rc = run_panel<T>(s, A, lda, n, kb, wk, ipiv, info, mv, sch.panel_cus, st))) return rc;
@@ -367,13 +377,13 @@ int factor_impl(int n, void* A, int lda, lu_precision_t prec, int* ipiv, const l
     s->last_info = info;
     switch (prec) {
     case LU_FP64:
-        return execute<double, _Float16>(s, n, reinterpret_cast<double*>(A), lda, ipiv, info, sch, stream, false);
+        return execute<double, _Float16>(s, n, reinterpret_cast<double*>(A), lda, ipiv, info, sch, prec, stream, false);
     case LU_FP32:
-        return execute<float, _Float16>(s, n, reinterpret_cast<float*>(A), lda, ipiv, info, sch, stream, false);
+        return execute<float, _Float16>(s, n, reinterpret_cast<float*>(A), lda, ipiv, info, sch, prec, stream, false);
     case LU_MIXED_FP16:
-        return execute<float, _Float16>(s, n, reinterpret_cast<float*>(A), lda, ipiv, info, sch, stream, true);
+        return execute<float, _Float16>(s, n, reinterpret_cast<float*>(A), lda, ipiv, info, sch, prec, stream, true);
     case LU_MIXED_BF16:
-        return execute<float, __bf16>(s, n, reinterpret_cast<float*>(A), lda, ipiv, info, sch, stream, true);
+        return execute<float, __bf16>(s, n, reinterpret_cast<float*>(A), lda, ipiv, info, sch, prec, stream, true);
     }
     return -5;
 }

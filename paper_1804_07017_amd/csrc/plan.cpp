@@ -26,15 +26,14 @@ struct Access {
 
 inline bool overlap(int a0, int a1, int b0, int b1) { return a0 < b1 && b0 < a1 && a0 < a1 && b0 < b1; }
 
-Access access_of(const PlanTask& t, int b, int n) {
+Access access_of(const PlanTask& t, const std::vector<int>& starts) {
     Access a{t.col_begin, t.col_end, 0, 0, -1, -1};
     switch (t.kind) {
     case kTaskPanel:
         a.ipiv_w = t.step;
         break;
     case kTaskUpdate: {
-        int p0 = t.step * b, p1 = std::min(n, p0 + b);
-        a.r0 = p0; a.r1 = p1;          // reads the factored panel k (L11, L21)
+        a.r0 = starts[t.step]; a.r1 = starts[t.step + 1];   // reads the factored panel k (L11, L21)
         a.ipiv_r = t.step;
         break;
     }
@@ -57,14 +56,49 @@ bool conflicts(const Access& e, const Access& l) {
 
 }  // namespace
 
+int taper_width(int prec, int trailing) {
+    // Early termination, done statically: the panel narrows as the trailing
+    // matrix shrinks, so that in the tail the factorization of the next panel
+    // stays short next to the update it overlaps.  The widths are the block
+    // sizes that are fastest for a whole factorization of that size on this
+    // GPU (the schedule sweep), per precision class.
+    if (prec == 0) return trailing <= 12288 ? 128 : 1 << 30;      // FP64
+    return trailing <= 16384 ? 128 : 1 << 30;                     // FP32 and mixed
+}
+
+std::vector<int> panel_starts(int n, int b, int taper, int prec) {
+    std::vector<int> st;
+    if (n <= 0 || b < 1) return st;
+    int c = 0;
+    st.push_back(0);
+    while (c < n) {
+        int w = b;
+        if (taper > 0) w = std::min(w, taper_width(prec, n - c));
+        c = std::min(n, c + w);
+        st.push_back(c);
+    }
+    return st;
+}
+
 int build_plan(int n, int b, int depth, std::vector<PlanTask>& out) {
     out.clear();
     if (n < 0) return -1;
     if (b < 1) return -2;
     if (depth < 0 || depth > 2) return -3;
+    return build_plan(n, panel_starts(n, b, 0, 0), depth, out);
+}
+
+int build_plan(int n, const std::vector<int>& starts, int depth, std::vector<PlanTask>& out) {
+    out.clear();
+    if (n < 0) return -1;
+    if (depth < 0 || depth > 2) return -3;
     if (n == 0) return 0;
-    const int N = (n + b - 1) / b;
-    auto panel_cols = [&](int j, int& c0, int& c1) { c0 = j * b; c1 = std::min(n, c0 + b); };
+    const int N = (int)starts.size() - 1;
+    if (N < 1 || starts[0] != 0 || starts[N] != n) return -4;
+    for (int j = 0; j < N; ++j)
+        if (starts[j + 1] <= starts[j]) return -4;
+    auto panel_cols = [&](int j, int& c0, int& c1) { c0 = starts[j]; c1 = starts[j + 1]; };
+    auto col_of = [&](int j) { return j >= N ? n : starts[j]; };   // first column of panel j (n past the end)
     auto push = [&](int kind, int step, int c0, int c1, int stream) {
         if (c0 >= c1) return;
         PlanTask t{};
@@ -78,7 +112,7 @@ int build_plan(int n, int b, int depth, std::vector<PlanTask>& out) {
             panel_cols(k, c0, c1);
             push(kTaskPanel, k, c0, c1, 0);
             push(kTaskUpdate, k, c1, n, 0);
-            if (k >= 1) push(kTaskLswap, k, 0, k * b, 0);
+            if (k >= 1) push(kTaskLswap, k, 0, c0, 0);
         }
     } else {
         const int d = depth;
@@ -93,19 +127,19 @@ int build_plan(int n, int b, int depth, std::vector<PlanTask>& out) {
         for (int k = 0; k < N; ++k) {
             const int j = k + d;                         // panel factored during step k's bulk update
             if (j < N) { panel_cols(j, c0, c1); push(kTaskUpdate, k, c0, c1, 0); }   // TU_k, left part
-            push(kTaskUpdate, k, std::min(n, (k + d + 1) * b), n, 0);                 // TU_k, right part
+            push(kTaskUpdate, k, col_of(k + d + 1), n, 0);                            // TU_k, right part
             if (j < N) {
                 panel_cols(j, c0, c1);
                 for (int i = k + 1; i < j; ++i) push(kTaskUpdate, i, c0, c1, 1);
                 push(kTaskPanel, j, c0, c1, 1);
             }
-            if (k >= 1) push(kTaskLswap, k, 0, k * b, 2);
+            if (k >= 1) push(kTaskLswap, k, 0, starts[k], 2);
         }
     }
     // Derive cross-stream waits from data accesses.
     const int T = (int)out.size();
     std::vector<Access> acc(T);
-    for (int i = 0; i < T; ++i) acc[i] = access_of(out[i], b, n);
+    for (int i = 0; i < T; ++i) acc[i] = access_of(out[i], starts);
     // covered[s][u]: latest task of stream u that stream s already waits for
     int covered[kPlanStreams][kPlanStreams];
     for (auto& r : covered) for (int& c : r) c = -1;
@@ -131,10 +165,9 @@ int build_plan(int n, int b, int depth, std::vector<PlanTask>& out) {
 
 }  // namespace lu
 
-extern "C" int lu_plan_build(int n, int b, int depth, lu_plan_task_t* out, int max_tasks) {
-    std::vector<lu::PlanTask> v;
-    int r = lu::build_plan(n, b, depth, v);
-    if (r < 0) return r;
+namespace {
+
+int export_plan(const std::vector<lu::PlanTask>& v, lu_plan_task_t* out, int max_tasks) {
     if ((int)v.size() > max_tasks) return -5;
     for (size_t i = 0; i < v.size(); ++i) {
         lu_plan_task_t& o = out[i];
@@ -145,4 +178,37 @@ extern "C" int lu_plan_build(int n, int b, int depth, lu_plan_task_t* out, int m
         o.record = v[i].record;
     }
     return (int)v.size();
+}
+
+}  // namespace
+
+extern "C" int lu_plan_build(int n, int b, int depth, lu_plan_task_t* out, int max_tasks) {
+    std::vector<lu::PlanTask> v;
+    int r = lu::build_plan(n, b, depth, v);
+    if (r < 0) return r;
+    return export_plan(v, out, max_tasks);
+}
+
+extern "C" int lu_plan_panels(int n, int b, int taper, int prec, int* starts, int max_starts) {
+    if (n < 0) return -1;
+    if (b < 1) return -2;
+    if (prec < 0 || prec > 3) return -4;
+    if (n == 0) return 0;
+    const std::vector<int> st = lu::panel_starts(n, b, taper, prec);
+    const int N = (int)st.size() - 1;
+    if (!starts || max_starts < N + 1) return -5;
+    for (int j = 0; j <= N; ++j) starts[j] = st[j];
+    return N;
+}
+
+extern "C" int lu_plan_build_panels(int n, const int* starts, int npanels, int depth, lu_plan_task_t* out,
+                                    int max_tasks) {
+    if (n < 0) return -1;
+    if (n > 0 && (!starts || npanels < 1)) return -4;
+    std::vector<int> st;
+    if (n > 0) st.assign(starts, starts + npanels + 1);
+    std::vector<lu::PlanTask> v;
+    int r = lu::build_plan(n, st, depth, v);
+    if (r < 0) return r;
+    return export_plan(v, out, max_tasks);
 }

@@ -16,6 +16,13 @@ struct PlanTask {
     int record;
 };
 
+// Panel boundaries: starts[0] = 0 < starts[1] < ... < starts[N] = n.
+// taper <= 0: every panel b wide (the last one ragged); taper > 0: the width
+// of panel j is min(b, taper_width(prec, n - starts[j])).
+std::vector<int> panel_starts(int n, int b, int taper, int prec);
+int taper_width(int prec, int trailing);
+
 int build_plan(int n, int b, int depth, std::vector<PlanTask>& out);
+int build_plan(int n, const std::vector<int>& starts, int depth, std::vector<PlanTask>& out);
 
 }  // namespace lu

@@ -103,7 +103,7 @@ void try_default() {
     load_file(default_path().c_str());
 }
 
-lu_schedule_t fixed_default() { return lu_schedule_t{256, 1, 16}; }
+lu_schedule_t fixed_default() { return lu_schedule_t{256, 1, 16, 0}; }
 
 }  // namespace
 

@@ -51,7 +51,11 @@ struct DeviceState {
     Buffer solve_moves, flags, partial, ir_r, ir_x32, ir_a32, ir_a64, ir_norms, ir_ipiv, ir_b;
     int trsv_epoch = 0;
 
-    std::map<long long, std::vector<PlanTask>> plans;
+    struct Plan {
+        std::vector<int> starts;        // panel boundaries, starts[N] = n
+        std::vector<PlanTask> tasks;
+    };
+    std::map<long long, Plan> plans;
 };
 
 DeviceState* device_state(int* err);

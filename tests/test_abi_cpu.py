@@ -67,7 +67,11 @@ def test_selector_file_errors(tmp_path):
 
 
 # ------------------------------------------------------------- plan checks
-def _access(t, b, n):
+def _uniform_starts(n, b):
+    return list(range(0, n, b)) + [n]
+
+
+def _access(t, starts):
     """(write columns, read columns, ipiv written, ipiv read) of a task."""
     w = set(range(t["col_begin"], t["col_end"]))
     r = set()
@@ -76,7 +80,7 @@ def _access(t, b, n):
         ipw = t["step"]
     elif t["kind"] == lu.LU_TASK_UPDATE:
         k = t["step"]
-        r = set(range(k * b, min(n, k * b + b)))
+        r = set(range(starts[k], starts[k + 1]))
         ipr = k
     else:
         ipr = t["step"]
@@ -97,25 +101,26 @@ def _happens_before(tasks):
     return before
 
 
-@pytest.mark.parametrize("n,b,depth", [(10, 4, 0), (10, 4, 1), (13, 4, 2), (64, 16, 1), (70, 16, 2),
-                                       (33, 8, 2), (8, 8, 1), (5, 8, 2), (100, 32, 1)])
-def test_plan_is_race_free_and_complete(n, b, depth):
-    rc, tasks = lu.lu_plan_build(n, b, depth)
-    assert rc == len(tasks) > 0
-    N = (n + b - 1) // b
+def _check_plan(n, starts, depth, tasks):
+    N = len(starts) - 1
     # every panel factored once; every (step, column) pair of the trailing
     # matrix updated exactly once; every left swap applied once
     panels = [t["step"] for t in tasks if t["kind"] == lu.LU_TASK_PANEL]
     assert sorted(panels) == list(range(N))
+    for t in tasks:
+        if t["kind"] == lu.LU_TASK_PANEL:
+            assert (t["col_begin"], t["col_end"]) == (starts[t["step"]], starts[t["step"] + 1])
     cover = {}
     for t in tasks:
         if t["kind"] == lu.LU_TASK_UPDATE:
             for c in range(t["col_begin"], t["col_end"]):
                 cover[(t["step"], c)] = cover.get((t["step"], c), 0) + 1
     for k in range(N):
-        for c in range(min(n, (k + 1) * b), n):
+        for c in range(starts[k + 1], n):
             assert cover.get((k, c)) == 1, (k, c)
-    assert len(cover) == sum(max(0, n - min(n, (k + 1) * b)) for k in range(N))
+    assert len(cover) == sum(n - starts[k + 1] for k in range(N))
+    lswaps = sorted((t["step"], t["col_begin"], t["col_end"]) for t in tasks if t["kind"] == lu.LU_TASK_LSWAP)
+    assert lswaps == [(k, 0, starts[k]) for k in range(1, N)]
     if depth == 0:
         assert all(t["stream"] == 0 for t in tasks)
     else:
@@ -127,7 +132,7 @@ def test_plan_is_race_free_and_complete(n, b, depth):
         assert all(tasks[w]["stream"] != t["stream"] for w in t["waits"])
     # race freedom: tasks not ordered by happens-before touch disjoint data
     hb = _happens_before(tasks)
-    acc = [_access(t, b, n) for t in tasks]
+    acc = [_access(t, starts) for t in tasks]
     for i in range(len(tasks)):
         for j in range(i):
             if j in hb[i]:
@@ -139,7 +144,55 @@ def test_plan_is_race_free_and_complete(n, b, depth):
             assert pwj is None or pwj != pri
 
 
-def _run_task(A, ipiv, t, b, n):
+@pytest.mark.parametrize("n,b,depth", [(10, 4, 0), (10, 4, 1), (13, 4, 2), (64, 16, 1), (70, 16, 2),
+                                       (33, 8, 2), (8, 8, 1), (5, 8, 2), (100, 32, 1)])
+def test_plan_is_race_free_and_complete(n, b, depth):
+    rc, tasks = lu.lu_plan_build(n, b, depth)
+    assert rc == len(tasks) > 0
+    _check_plan(n, _uniform_starts(n, b), depth, tasks)
+    # the same plan from explicit uniform boundaries
+    rc2, tasks2 = lu.lu_plan_build_panels(n, _uniform_starts(n, b), depth)
+    assert rc2 == rc and tasks2 == tasks
+
+
+@pytest.mark.parametrize("starts,depth", [([0, 8, 12, 14, 15], 1), ([0, 8, 12, 14, 15], 2),
+                                          ([0, 3, 11, 12, 20, 21], 2), ([0, 16, 24, 28, 30, 31], 0),
+                                          ([0, 1], 2), ([0, 1, 2], 2)])
+def test_plan_with_variable_panels_is_race_free_and_complete(starts, depth):
+    n = starts[-1]
+    rc, tasks = lu.lu_plan_build_panels(n, starts, depth)
+    assert rc == len(tasks) > 0
+    _check_plan(n, starts, depth, tasks)
+
+
+def test_taper_boundaries():
+    """The early-termination taper: panels never wider than b, 128 wide once
+    the trailing size drops to the precision's threshold, exact cover."""
+    thresholds = {0: 12288, 1: 16384, 2: 16384, 3: 16384}
+    for prec, t128 in thresholds.items():
+        for n, b in [(32768, 256), (12000, 256), (20000, 512), (45000, 512), (3000, 64), (700, 128)]:
+            rc, st = lu.lu_plan_panels(n, b, 1, prec)
+            assert rc == len(st) - 1 and st[0] == 0 and st[-1] == n
+            for j in range(rc):
+                w, r = st[j + 1] - st[j], n - st[j]
+                want = b if r > t128 else min(b, 128)
+                assert w == min(want, r), (prec, n, b, j, w)
+            # taper off: uniform b
+            rc0, st0 = lu.lu_plan_panels(n, b, -1, prec)
+            assert st0 == _uniform_starts(n, b)
+    assert lu.lu_plan_panels(0, 256, 1, 0) == (0, [])
+    assert lu.lu_plan_panels(-1, 256, 1, 0)[0] == -1
+    assert lu.lu_plan_panels(10, 0, 1, 0)[0] == -2
+    assert lu.lu_plan_panels(10, 4, 1, 7)[0] == -4
+    assert lu.lu_plan_panels(100, 8, 1, 0, max_starts=5)[0] == -5
+    # boundaries that are not strictly increasing from 0 to n are rejected
+    assert lu.lu_plan_build_panels(10, [0, 5, 5, 10], 1)[0] == -4
+    assert lu.lu_plan_build_panels(10, [0, 5, 9], 1)[0] == -4
+    assert lu.lu_plan_build_panels(10, [1, 5, 10], 1)[0] == -4
+    assert lu.lu_plan_build_panels(10, [0, 5, 10], 3)[0] == -3
+
+
+def _run_task(A, ipiv, t, starts, n):
     """Execute one plan task on the numpy matrix A (FP64) in place."""
     k = t["step"]
     c0, c1 = t["col_begin"], t["col_end"]
@@ -154,7 +207,7 @@ def _run_task(A, ipiv, t, b, n):
                 A[d + 1:, d] /= A[d, d]
             A[d + 1:, d + 1:j1] -= np.outer(A[d + 1:, d], A[d, d + 1:j1])
     elif t["kind"] == lu.LU_TASK_UPDATE:
-        kb, w = k * b, min(b, n - k * b)
+        kb, w = starts[k], starts[k + 1] - starts[k]
         for d in range(kb, kb + w):
             p = ipiv[d]
             if p != d:
@@ -163,7 +216,7 @@ def _run_task(A, ipiv, t, b, n):
         A[kb:kb + w, c0:c1] = np.linalg.solve(L11, A[kb:kb + w, c0:c1])
         A[kb + w:, c0:c1] -= A[kb + w:, kb:kb + w] @ A[kb:kb + w, c0:c1]
     else:
-        kb, w = k * b, min(b, n - k * b)
+        kb, w = starts[k], starts[k + 1] - starts[k]
         for d in range(kb, kb + w):
             p = ipiv[d]
             if p != d:
@@ -184,12 +237,18 @@ def _random_legal_order(tasks, rng):
     return order
 
 
-@pytest.mark.parametrize("n,b,depth", [(24, 4, 1), (30, 8, 2), (37, 8, 1), (37, 8, 2), (40, 8, 0)])
-def test_plan_executes_to_the_oracle_result_in_any_legal_order(n, b, depth):
+@pytest.mark.parametrize("n,starts,depth", [(24, 4, 1), (30, 8, 2), (37, 8, 1), (37, 8, 2), (40, 8, 0),
+                                            (37, [0, 12, 20, 26, 30, 33, 35, 36, 37], 2),
+                                            (37, [0, 12, 20, 26, 30, 33, 35, 36, 37], 1)])
+def test_plan_executes_to_the_oracle_result_in_any_legal_order(n, starts, depth):
     import oracle
     import synth
     A0 = np.array(synth.uniform(n, seed=n), order="F")
-    rc, tasks = lu.lu_plan_build(n, b, depth)
+    if isinstance(starts, int):
+        rc, tasks = lu.lu_plan_build(n, starts, depth)
+        starts = _uniform_starts(n, starts)
+    else:
+        rc, tasks = lu.lu_plan_build_panels(n, starts, depth)
     results = []
     rng = np.random.default_rng(0)
     for trial in range(4):
@@ -197,7 +256,7 @@ def test_plan_executes_to_the_oracle_result_in_any_legal_order(n, b, depth):
         ipiv = np.zeros(n, dtype=np.int64)
         order = range(len(tasks)) if trial == 0 else _random_legal_order(tasks, rng)
         for i in order:
-            _run_task(A, ipiv, tasks[i], b, n)
+            _run_task(A, ipiv, tasks[i], starts, n)
         results.append((A, ipiv))
     for A, ipiv in results[1:]:
         assert np.array_equal(A, results[0][0]) and np.array_equal(ipiv, results[0][1])

@@ -11,14 +11,16 @@ from tests import pins
 pytestmark = pytest.mark.gpu
 
 
-def _factor(gpu, A_np, b, depth, panel_cus=16, prec=0, lda=None):
+def _factor(gpu, A_np, b, depth, panel_cus=16, prec=0, lda=None, taper=-1):
+    """Factor on the GPU; taper -1 (default here) keeps every panel b wide, so
+    that each test exercises the block size it names."""
     import torch
     n = A_np.shape[0]
     dt = torch.float64 if prec == 0 else torch.float32
     dA = gpu.to_device(np.asarray(A_np), dt, lda=lda)
     ipiv = torch.zeros(max(n, 1), dtype=torch.int32, device="cuda")
     info = torch.zeros(1, dtype=torch.int32, device="cuda")
-    rc = gpu.lu_factor_ex(dA, ipiv, prec=prec, sched=(b, depth, panel_cus), d_info=info)
+    rc = gpu.lu_factor_ex(dA, ipiv, prec=prec, sched=(b, depth, panel_cus, taper), d_info=info)
     assert rc == 0
     torch.cuda.synchronize()
     rc2, _ = gpu.lu_factor_info()
@@ -75,6 +77,59 @@ def test_schedule_invariance_bitwise(gpu):
                 ref = (LU, ipiv)
             else:
                 assert np.array_equal(LU, ref[0]) and np.array_equal(ipiv, ref[1]), (depth, cus)
+
+
+@pytest.mark.parametrize("n,b,depth", [(3000, 256, 2), (2100, 512, 1), (1000, 128, 0)])
+def test_taper_matches_oracle(gpu, n, b, depth):
+    """Early-termination taper (panels narrowing to 128 columns once the
+    trailing matrix is small): the same factorization as the oracle's."""
+    A = synth.uniform(n, seed=n + 7)
+    LU, ipiv, info = _factor(gpu, A, b, depth, taper=1)
+    oLU, oip, oinfo = oracle.getrf(A, nthreads=8)
+    assert info == oinfo == 0
+    assert np.array_equal(ipiv, oip)
+    assert np.abs(LU - oLU).max() <= 1e-11 * max(1.0, np.abs(oLU).max())
+
+
+def test_taper_schedule_invariance_bitwise(gpu):
+    """With the taper, panel widths 256 -> 128 are fixed by n and the
+    precision, so depth and CU share leave every bit of the result unchanged."""
+    import torch
+    n = 17000
+    A = synth.uniform(n, seed=5)
+    dA0 = gpu.to_device(A)
+    del A
+    ref = None
+    for depth, cus in ((0, 16), (1, 8), (2, 32)):
+        dA = dA0.clone()
+        ipiv = torch.zeros(n, dtype=torch.int32, device="cuda")
+        assert gpu.lu_factor_ex(dA, ipiv, sched=(256, depth, cus, 1)) == 0
+        torch.cuda.synchronize()
+        assert gpu.lu_factor_info() == (0, 0)
+        if ref is None:
+            ref = (dA, ipiv)
+        else:
+            assert torch.equal(dA, ref[0]) and torch.equal(ipiv, ref[1]), (depth, cus)
+    rf = _device_residual(gpu, dA0, ref[0], ref[1].cpu().numpy())
+    assert rf <= 16.0, rf
+
+
+def test_mixed_taper_ir(gpu):
+    """Mixed-precision LU with the taper (128-wide tail panels, the library
+    default), refined to the FP64 acceptance test."""
+    import torch
+    n = 5000
+    A = synth.dominant(n, seed=3)
+    b = synth.rhs(n, seed=3)[:, 0]
+    dA = gpu.to_device(A)
+    dB = torch.from_numpy(np.ascontiguousarray(b)).cuda()
+    dX = torch.zeros(n, dtype=torch.float64, device="cuda")
+    rc, sch = gpu.lu_schedule_default(n, gpu.LU_MIXED_FP16)
+    assert rc == 0 and sch[3] == 1
+    st, it, res = gpu.lu_solve_ir(dA, dB, dX, prec=gpu.LU_MIXED_FP16, max_iter=10)
+    torch.cuda.synchronize()
+    assert st == 0 and res <= 16.0, (st, it, res)
+    assert oracle.r_hpl(A, dX.cpu().numpy(), b) <= 16.0
 
 
 def test_zero_column_and_zero_matrix_info(gpu):
@@ -157,10 +212,10 @@ def test_c2_8192_lookahead_and_solve(gpu):
     n = 8192
     A = synth.uniform(n, seed=1)
     b = synth.rhs(n, seed=1)
-    for bs in (128, 256):
+    for sched in ((128, 1, 16, -1), (256, 1, 16, -1), (256, 2, 32, 1)):
         dA = gpu.to_device(A)
         ipiv = torch.zeros(n, dtype=torch.int32, device="cuda")
-        assert gpu.lu_factor_ex(dA, ipiv, sched=(bs, 1, 16)) == 0
+        assert gpu.lu_factor_ex(dA, ipiv, sched=sched) == 0
         torch.cuda.synchronize()
         assert gpu.lu_factor_info() == (0, 0)
         # scaled factor residual with a library GEMM (rocBLAS via torch) on the device
@@ -200,8 +255,8 @@ def _device_residual(gpu, dA0, dLU, ipiv):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("b,depth,cus", [(256, 1, 16), (512, 2, 8)])
-def test_c3_32768_uniform(gpu, b, depth, cus):
+@pytest.mark.parametrize("b,depth,cus,taper", [(256, 1, 16, -1), (512, 2, 8, -1), (256, 2, 32, 1)])
+def test_c3_32768_uniform(gpu, b, depth, cus, taper):
     """Full-size FP64 look-ahead LU: scaled residual with a library GEMM, the
     pivots are a legal permutation, every multiplier is bounded by 1, and the
     first panel's pivots equal the oracle's (a plain column search over A)."""
@@ -213,7 +268,7 @@ def test_c3_32768_uniform(gpu, b, depth, cus):
     del A
     dA = dA0.clone()
     ipiv = torch.zeros(n, dtype=torch.int32, device="cuda")
-    assert gpu.lu_factor_ex(dA, ipiv, sched=(b, depth, cus)) == 0
+    assert gpu.lu_factor_ex(dA, ipiv, sched=(b, depth, cus, taper)) == 0
     torch.cuda.synchronize()
     assert gpu.lu_factor_info() == (0, 0)
     ip = ipiv.cpu().numpy()
