@@ -7,19 +7,20 @@
 // holds rows g*R + q*256 + t (q < RPT).  The panel is processed in column
 // blocks of NB columns, each held in registers while it is factored:
 //
-//   for each column j of the block (one device-wide barrier per column):
+//   for each column j of the block (one device-wide exchange per column):
 //     each work-group finds its arg-max of |a| over rows >= the diagonal row d
 //     (ties -> smallest row), publishes value, row index and that row's NB
-//     block values; the owner of row d publishes row d.  After the barrier
-//     every work-group picks the same global winner p, swaps rows d and p
-//     inside the register block, scales the sub-column by the pivot (true
-//     division) and applies the rank-1 update to the remaining block columns.
-//   after the block (one more barrier):
-//     the work-group owning the block's diagonal rows applies the block's
-//     interchanges to the other panel columns and solves the unit-lower
-//     NB x NB system for the block's U rows of the columns to its right
-//     (RL2 restricted to the panel); then every work-group updates its own
-//     rows of those columns with the block's L (RL3 restricted to the panel).
+//     block values; the owner of row d publishes row d.  Once every
+//     work-group's words have arrived, each picks the same global winner p,
+//     swaps rows d and p inside the register block, scales the sub-column by
+//     the pivot (true division) and applies the rank-1 update to the
+//     remaining block columns.
+//   after the block (one device-wide barrier):
+//     every work-group applies the block's interchanges to its share of the
+//     other panel columns and solves the unit-lower NB x NB system for the
+//     block's U rows of those columns to its right (RL2 restricted to the
+//     panel); then every work-group updates its own rows of those columns
+//     with the block's L (RL3 restricted to the panel).
 //
 // At the end work-group 0 composes the panel's w interchanges into one
 // gather/scatter list (see compose_moves) used by the trailing-update and
@@ -88,7 +89,7 @@ struct PanelShared {
     T red_v[2][kPanelThreads / kWave];
     int red_i[2][kPanelThreads / kWave];
     int orslot[2 * (kPanelThreads / kWave)];
-    unsigned xbuf[kMaxPanelWgs * (1 + Xch<T, NB>::WPV) + 2 * Xch<T, NB>::DR];   // payloads of one step
+    unsigned xbuf[kMaxPanelWgs * Xch<T, NB>::SR + Xch<T, NB>::DR];   // payloads of one step
     T fin[NB][FinCfg<T, NB, RPT>::cols];   // finished block columns of this work-group's rows
     T L[NB][NB + 1];
     T U[kMovesMaxW][NB];          // in-panel update: the block's U rows, transposed
@@ -390,23 +391,37 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
             int poll = 0;
             bool failed = false;
             {
-                constexpr int HW = 1 + X::WPV;                         // header words per slot
-                static_assert(kMaxPanelWgs * HW + X::DR <= kPanelThreads, "one exchange word per thread");
-                const int nh = P * HW;
-                const int total = nh + X::DR;
-                const unsigned long long* src = (tid < nh)
-                    ? xa + (size_t)(tid / HW) * X::SW + (tid % HW)
-                    : xa + (size_t)kMaxPanelWgs * X::SW + (tid - nh);
-                // every thread spins on its own word (bounded by the wall clock;
-                // thread 0 also watches the error word), then one barrier
-                bool done = tid >= total;
+                // every work-group's slot (header and candidate row) and row d:
+                // thread t polls words t, t + threads, ... until all carry this
+                // step's tag (bounded wait; thread 0 also watches the error
+                // word), then one barrier
+                constexpr int MAXW = (kMaxPanelWgs * X::SR + X::DR + kPanelThreads - 1) / kPanelThreads;
+                static_assert(MAXW <= 32, "poll mask");
+                const int ns = P * X::SR;
+                const int total = ns + X::DR;
+                int off[MAXW];                              // word offsets in this parity's area
+                unsigned pending = 0;
+#pragma unroll
+                for (int k = 0; k < MAXW; ++k) {
+                    const int wi = min(tid + k * kPanelThreads, total - 1);
+                    off[k] = wi < ns ? (wi / X::SR) * X::SW + (wi % X::SR) : kMaxPanelWgs * X::SW + (wi - ns);
+                    if (tid + k * kPanelThreads < total) pending |= 1u << k;
+                }
                 int st = 0;
-                while (!done) {
-                    const unsigned long long wv = xload(src);
+                while (pending) {
+                    unsigned long long wv[MAXW];
+#pragma unroll
+                    for (int k = 0; k < MAXW; ++k) wv[k] = ((pending >> k) & 1u) ? xload(xa + off[k]) : 0ull;
                     unsigned errw = 0;
                     if (tid == 0) errw = xload(a.sync + 1);
-                    if ((unsigned)(wv >> 32) == tag) { sh.xbuf[tid] = (unsigned)wv; done = true; }
-                    else if (errw != 0u || wall_clock64() - t0 > a.spin_limit) { st = 3; break; }
+#pragma unroll
+                    for (int k = 0; k < MAXW; ++k) {
+                        if (((pending >> k) & 1u) && (unsigned)(wv[k] >> 32) == tag) {
+                            sh.xbuf[tid + k * kPanelThreads] = (unsigned)wv[k];
+                            pending &= ~(1u << k);
+                        }
+                    }
+                    if (pending && (errw != 0u || wall_clock64() - t0 > a.spin_limit)) { st = 3; break; }
                 }
                 st = wg_or(st, sh.orslot, poll & 1, kPanelThreads / kWave);
                 ++poll;
@@ -419,13 +434,14 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
             // 4. global winner, computed by every wave from the headers (same
             //    decision everywhere: largest magnitude, then smallest row); the
             //    winning row's owner follows from the row distribution
+            constexpr int HW = 1 + X::WPV;                 // header words per slot
+            const int ns = P * X::SR;                      // xbuf: slots, then row d
             int p, wg;
             {
-                constexpr int HW = 1 + X::WPV;
                 T v = T(-1);
                 int i = 0x7fffffff;
                 if (lane < P) {
-                    const unsigned* sw = &sh.xbuf[lane * HW];
+                    const unsigned* sw = &sh.xbuf[lane * X::SR];
                     i = (int)sw[0];
                     v = get_value(&sw[1], (T*)nullptr);
                 }
@@ -433,30 +449,11 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
                 if (i == 0x7fffffff) { p = d; wg = -1; }   // no finite candidate: keep row d
                 else { p = i; wg = i / R; }
             }
-            // 5. phase B: the winning work-group's block row
-            const int nhw = P * (1 + X::WPV);                          // xbuf: headers, row d, winner row
-            const int ww = nhw + X::DR;
-            if (wg >= 0) {
-                bool done = tid >= X::DR;
-                int st = 0;
-                while (!done) {
-                    const unsigned long long wv = xload(xa + (size_t)wg * X::SW + 1 + X::WPV + tid);
-                    unsigned errw = 0;
-                    if (tid == 0) errw = xload(a.sync + 1);
-                    if ((unsigned)(wv >> 32) == tag) { sh.xbuf[ww + tid] = (unsigned)wv; done = true; }
-                    else if (errw != 0u || wall_clock64() - t0 > a.spin_limit) { st = 3; break; }
-                }
-                st = wg_or(st, sh.orslot, poll & 1, kPanelThreads / kWave);
-                ++poll;
-                if (st & 2) {
-                    if (tid == 0) xstore(a.sync + 1, 1u);
-                    return;
-                }
-            }
-            // block-row values of row d and of the pivot row, decoded from xbuf
-            auto drow_at = [&](int t) -> T { return get_value(&sh.xbuf[nhw + t * X::WPV], (T*)nullptr); };
+            // 5. block-row values of row d and of the pivot row (the winning
+            //    work-group's candidate row), decoded from xbuf
+            auto drow_at = [&](int t) -> T { return get_value(&sh.xbuf[ns + t * X::WPV], (T*)nullptr); };
             auto prow_at = [&](int t) -> T {
-                return wg >= 0 ? get_value(&sh.xbuf[ww + t * X::WPV], (T*)nullptr) : drow_at(t);
+                return wg >= 0 ? get_value(&sh.xbuf[wg * X::SR + HW + t * X::WPV], (T*)nullptr) : drow_at(t);
             };
             if (tid == 0) {
                 sh.piv[d] = p;
