@@ -16,6 +16,10 @@ Contents
 * ``r_hpl``: HPL-style scaled solve residual
   ||A x - b||_inf / (eps (||A||_inf ||x||_inf + ||b||_inf) n).
   Both use eps = 2**-53 (unit roundoff of binary64).
+* ``potrf``: ctypes wrapper over ``chol_oracle.c`` -- plain FP64 Cholesky
+  A = L L^T of the lower triangle, one column at a time (the unblocked form of
+  a factorization that fits the blocked skeleton of Sec. 3.1); ``r_chol``:
+  scaled residual ||A - L L^T||_F / (||A||_F n eps).
 * ``mlp``: FP64 forward/backward/Adam of the schedule-selector network.
 """
 from __future__ import annotations
@@ -28,6 +32,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lu_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "chol_oracle.c")]
 _LIB = os.path.join(_HERE, "liblu_oracle.so")
 
 EPS64 = 2.0 ** -53
@@ -35,11 +40,11 @@ EPS64 = 2.0 ** -53
 
 def build(force: bool = False) -> str:
     """Compile lu_oracle.c with gcc (separately rounded FP ops: -ffp-contract=off)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f) for f in _SRCS):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(
             ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-             "-pthread", "-o", tmp, _SRC, "-lm"])
+             "-pthread", "-o", tmp] + _SRCS + ["-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -58,6 +63,8 @@ def _load():
         lib.oracle_getrs.restype = ctypes.c_int
         lib.oracle_getrs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+        lib.oracle_potrf.restype = ctypes.c_int
+        lib.oracle_potrf.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -100,6 +107,30 @@ def getrs(LU: np.ndarray, ipiv: np.ndarray, B: np.ndarray) -> np.ndarray:
     if r != 0:
         raise ValueError("oracle_getrs: illegal argument %d" % -r)
     return X[:, 0] if vec else X
+
+
+def potrf(A: np.ndarray, nthreads: int = 1):
+    """Cholesky of the lower triangle of the SPD matrix A: returns (F, info)
+    where tril(F) = L and the strictly upper triangle of F is A's, untouched."""
+    n = A.shape[0]
+    if A.shape[1] != n:
+        raise ValueError("square matrix expected")
+    F = np.array(A, dtype=np.float64, order="F", copy=True)
+    F, lda = _as_colmajor(F)
+    info = _load().oracle_potrf(n, F.ctypes.data, max(lda, 1), int(nthreads))
+    if info < 0:
+        raise ValueError("oracle_potrf: illegal argument %d" % -info)
+    return F, info
+
+
+def r_chol(A: np.ndarray, F: np.ndarray, matmul=None) -> float:
+    """Scaled Cholesky residual ||A - L L^T||_F / (||A||_F n eps), L = tril(F)."""
+    n = A.shape[0]
+    if n == 0:
+        return 0.0
+    L = np.tril(F)
+    LLt = (matmul or np.matmul)(L, L.T)
+    return float(np.linalg.norm(A - LLt) / (np.linalg.norm(A) * n * EPS64))
 
 
 def perm_from_ipiv(ipiv: np.ndarray) -> np.ndarray:

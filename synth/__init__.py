@@ -73,6 +73,20 @@ def dominant(n: int, seed: int = 1, lda: int | None = None) -> np.ndarray:
     return A
 
 
+def spd(n: int, seed: int = 1, lda: int | None = None) -> np.ndarray:
+    """Symmetric positive definite workload for Cholesky: the symmetric part
+    (B + B^T)/2 of a uniform[-1,1) matrix B, with each diagonal entry set to
+    its row's absolute sum (strictly diagonally dominant, positive diagonal)."""
+    B = uniform(n, seed, lda)
+    A = B[:n, :n]
+    A[:] = (A + A.T) / 2.0
+    s = np.zeros(n)
+    for j in range(n):
+        s += np.abs(A[:, j])
+    A[np.arange(n), np.arange(n)] = s
+    return B
+
+
 def planted_factors(n: int, seed: int = 1, a_l: float = 0.1):
     """Return (L, U, perm) of the planted workload (dense float64 arrays)."""
     gl, gu, gp = rng(seed, STREAM_L), rng(seed, STREAM_U), rng(seed, STREAM_PERM)
