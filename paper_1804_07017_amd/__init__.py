@@ -58,6 +58,8 @@ _SIGS = {
     "lu_selector_grad": (_I, [_P, _P, _I, _P, _P]),
     "lu_release": (None, []),
     "lu_plan_build": (_I, [_I, _I, _I, ctypes.POINTER(PlanTask), _I]),
+    "chol_factor": (_I, [_I, _P, _I, _P]),
+    "chol_factor_ex": (_I, [_I, _P, _I, ctypes.POINTER(Schedule), _P, _P]),
     "lu_plan_panels": (_I, [_I, _I, _I, _I, ctypes.POINTER(_I), _I]),
     "lu_plan_build_panels": (_I, [_I, ctypes.POINTER(_I), _I, _I, ctypes.POINTER(PlanTask), _I]),
     "lu_k_panel": (_I, [_I, _I, _I, _P, _I, _P, _I, _P, _P]),
@@ -168,6 +170,17 @@ def lu_factor_ex(A, ipiv, prec=LU_FP64, sched=None, d_info=None, stream=None, n=
     n = A.shape[0] if n is None else n
     return load().lu_factor_ex(n, _ptr(A), _ld(A), int(prec), _ptr(ipiv), _sched(sched), _ptr(d_info),
                                _stream(stream))
+
+
+def chol_factor(A, stream=None, n=None):
+    """Cholesky A = L L^T (lower triangle, FP64) of the column-major device matrix A."""
+    n = A.shape[0] if n is None else n
+    return load().chol_factor(n, _ptr(A), _ld(A), _stream(stream))
+
+
+def chol_factor_ex(A, sched=None, d_info=None, stream=None, n=None):
+    n = A.shape[0] if n is None else n
+    return load().chol_factor_ex(n, _ptr(A), _ld(A), _sched(sched), _ptr(d_info), _stream(stream))
 
 
 def lu_factor_info():

@@ -58,6 +58,17 @@ constexpr int kMaxCand = 256;       // max panel work-groups
 constexpr int kNB = 16;             // panel register block width (panel.hip)
 }  // namespace
 
+int ensure_events(DeviceState* s, size_t count) {
+    // a factorization records each event at most once, so the ring never
+    // wraps onto an event that a later task still waits for
+    while (s->events.size() < count) {
+        hipEvent_t e;
+        LU_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        s->events.push_back(e);
+    }
+    return 0;
+}
+
 int ensure(Buffer& b, size_t bytes) {
     if (bytes <= b.bytes && b.ptr) return 0;
     if (b.ptr) {
@@ -272,9 +283,13 @@ int execute(DeviceState* s, int n, T* A, long long lda, int* ipiv, int* info, co
         rs = reinterpret_cast<float*>(s->rs.ptr);
         cs = reinterpret_cast<float*>(s->cs.ptr);
     }
+    size_t nrec = 0;
+    for (const PlanTask& t : *plan) nrec += t.record ? 1 : 0;
+    if ((rc = ensure_events(s, nrec + 2 * kPlanStreams + 2))) return rc;
+    const int ring = (int)s->events.size();
     hipStream_t streams[kPlanStreams] = {stream, s->panel_stream, s->swap_stream};
     // entry join: the library streams start after everything already on `stream`
-    hipEvent_t ev0 = s->events[s->ev_next]; s->ev_next = (s->ev_next + 1) % kEventRing;
+    hipEvent_t ev0 = s->events[s->ev_next]; s->ev_next = (s->ev_next + 1) % ring;
     LU_HIP(hipEventRecord(ev0, stream));
     LU_HIP(hipStreamWaitEvent(s->panel_stream, ev0, 0));
     LU_HIP(hipStreamWaitEvent(s->swap_stream, ev0, 0));
@@ -332,14 +347,14 @@ int execute(DeviceState* s, int n, T* A, long long lda, int* ipiv, int* info, co
         }
         if (t.record) {
             const int e = s->ev_next;
-            s->ev_next = (s->ev_next + 1) % kEventRing;
+            s->ev_next = (s->ev_next + 1) % ring;
             LU_HIP(hipEventRecord(s->events[e], st));
             ev_of[ti] = e;
         }
     }
     // exit join
     for (int u = 1; u < kPlanStreams; ++u) {
-        hipEvent_t ev1 = s->events[s->ev_next]; s->ev_next = (s->ev_next + 1) % kEventRing;
+        hipEvent_t ev1 = s->events[s->ev_next]; s->ev_next = (s->ev_next + 1) % ring;
         LU_HIP(hipEventRecord(ev1, streams[u]));
         LU_HIP(hipStreamWaitEvent(stream, ev1, 0));
     }

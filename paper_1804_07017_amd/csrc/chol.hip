@@ -1,0 +1,146 @@
+// Cholesky panel: the factorization of one column block of a symmetric
+// positive definite matrix, A = L L^T on the lower triangle.  Cholesky fits
+// the blocked skeleton of the paper (Sec. 3.1): per iteration the panel (the
+// diagonal block and the column block below it) is factored and the trailing
+// matrix receives a symmetric rank-b update; the look-ahead reorganization of
+// Sec. 4 applies unchanged, with no pivoting and so no row interchanges.
+//
+// One persistent launch of P work-groups (256 threads each) factors the m x w
+// panel (rows relative to the panel's diagonal, m >= w), in blocks of 16
+// columns.  Thread t of work-group g owns panel rows g*256 + t + s*256*P.
+// For each block [cb, cb+16):
+//   every work-group reads the block's 16 x 16 diagonal part and factors it in
+//   LDS (one wave; all groups compute the same values);
+//   each thread solves its rows below the diagonal part against it
+//   (x <- x L_bb^-T, forward substitution, true division);
+//   device-wide barrier (the solved rows of the panel's own diagonal region
+//   are the other operand of the next step, and no group still reads the
+//   diagonal part, which group 0 now overwrites with the factor);
+//   each thread updates its rows of the panel columns to the right of the
+//   block, lower triangle only (A[i,c] -= sum_k L[i,cb+k] L[c,cb+k], c <= i);
+//   device-wide barrier (the next block's diagonal part was written by
+//   whichever group owns it).
+// Every element receives its updates in the order of the unblocked algorithm
+// (column k = 0, 1, ... of the whole matrix), each as a separate multiply and
+// subtract, so the panel's result does not depend on P.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace lu {
+
+namespace {
+
+constexpr int kCholThreads = 256;
+constexpr int kCholNB = 16;
+constexpr int kCholMaxW = 512;
+
+template <typename T>
+__global__ __launch_bounds__(kCholThreads) void chol_panel_kernel(CholPanelArgs<T> a) {
+    __shared__ T D[kCholNB][kCholNB + 1];                  // the block's factored diagonal part
+    __shared__ T Ut[kCholMaxW - kCholNB][kCholNB + 1];     // L rows of the panel's diagonal region
+    __shared__ int s_bad;
+    const int tid = threadIdx.x;
+    const int g = blockIdx.x;
+    const int P = gridDim.x;
+    const int m = a.m, w = a.w;
+    const long long lda = a.lda;
+    T* __restrict__ A = a.A;
+    unsigned epoch = 0;
+    if (g == 0 && tid == 0 && a.sync_next) a.sync_next[0] = 0u;   // the next launch's barrier counter
+    const int stride = kCholThreads * P;
+
+    for (int cb = 0; cb < w; cb += kCholNB) {
+        const int nbw = min(kCholNB, w - cb);
+        // 1. the diagonal part, factored in LDS by wave 0
+        for (int e = tid; e < kCholNB * kCholNB; e += kCholThreads) {
+            const int r = e % kCholNB, c = e / kCholNB;
+            D[r][c] = (r < nbw && c <= r) ? A[(cb + r) + (long long)(cb + c) * lda] : T(0);
+        }
+        if (tid == 0) s_bad = 0;
+        __syncthreads();
+        if (tid < kWave) {
+            const int i = tid;           // lane i owns row i of the diagonal part
+            for (int j = 0; j < nbw; ++j) {
+                const T d = D[j][j];
+                const T r = sqrt(d);
+                if (!(d > T(0)) && i == 0 && s_bad == 0) s_bad = j + 1;
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                if (i == j) D[j][j] = r;
+                if (i > j && i < nbw) D[i][j] = D[i][j] / r;            // column j of L
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                if (i > j && i < nbw) {
+                    const T lij = D[i][j];
+                    for (int c = j + 1; c <= i; ++c) D[i][c] = D[i][c] - lij * D[c][j];
+                }
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            }
+        }
+        __syncthreads();
+        // 2. rows below the diagonal part: x <- x L_bb^-T
+        for (int i = cb + nbw + g * kCholThreads + tid; i < m; i += stride) {
+            T x[kCholNB];
+#pragma unroll
+            for (int c = 0; c < kCholNB; ++c) x[c] = (c < nbw) ? A[i + (long long)(cb + c) * lda] : T(0);
+#pragma unroll
+            for (int c = 0; c < kCholNB; ++c) {
+                if (c < nbw) {
+                    T v = x[c];
+#pragma unroll
+                    for (int k = 0; k < c; ++k) v = v - x[k] * D[c][k];
+                    x[c] = v / D[c][c];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < kCholNB; ++c)
+                if (c < nbw) A[i + (long long)(cb + c) * lda] = x[c];
+        }
+        // every group has read the diagonal part (step 1) before group 0
+        // overwrites it with the factor
+        if (grid_barrier(a.sync, a.sync + 1, ++epoch, a.spin_limit)) return;
+        if (g == 0) {
+            for (int e = tid; e < kCholNB * kCholNB; e += kCholThreads) {
+                const int r = e % kCholNB, c = e / kCholNB;
+                if (r < nbw && c <= r) A[(cb + r) + (long long)(cb + c) * lda] = D[r][c];
+            }
+            if (tid == 0 && s_bad != 0 && a.info) atomicCAS(a.info, 0, a.info_col_base + cb + s_bad);
+        }
+        const int right0 = cb + nbw;
+        if (right0 >= w) break;
+        // 3. the panel columns right of the block, lower triangle
+        for (int e = tid; e < (w - right0) * kCholNB; e += kCholThreads) {
+            const int c = e / kCholNB, k = e % kCholNB;
+            Ut[c][k] = (k < nbw) ? A[(right0 + c) + (long long)(cb + k) * lda] : T(0);
+        }
+        __syncthreads();
+        for (int i = right0 + g * kCholThreads + tid; i < m; i += stride) {
+            T l[kCholNB];
+#pragma unroll
+            for (int k = 0; k < kCholNB; ++k) l[k] = (k < nbw) ? A[i + (long long)(cb + k) * lda] : T(0);
+            const int cend = min(w, i + 1);
+            for (int c = right0; c < cend; ++c) {
+                T v = A[i + (long long)c * lda];
+#pragma unroll
+                for (int k = 0; k < kCholNB; ++k)
+                    if (k < nbw) v = v - l[k] * Ut[c - right0][k];
+                A[i + (long long)c * lda] = v;
+            }
+        }
+        if (grid_barrier(a.sync, a.sync + 1, ++epoch, a.spin_limit)) return;
+    }
+}
+
+}  // namespace
+
+template <typename T>
+int launch_chol_panel(const CholPanelArgs<T>& args, int wgs, hipStream_t stream) {
+    if (args.w < 1 || args.w > kCholMaxW || args.m < args.w || wgs < 1) return -1;
+    hipLaunchKernelGGL((chol_panel_kernel<T>), dim3(wgs), dim3(kCholThreads), 0, stream, args);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+template int launch_chol_panel<double>(const CholPanelArgs<double>&, int, hipStream_t);
+
+}  // namespace lu

@@ -46,10 +46,15 @@ __device__ __forceinline__ void tile_of(int tiles_m, int tiles_n, int& tm, int& 
     tn = r / gh;
 }
 
-template <typename T, int BK>
-__global__ __launch_bounds__(kThreads, 2) void gemm_nn_sub(int M, int N, int K, const T* __restrict__ A,
-                                                            int lda, const T* __restrict__ B, int ldb,
-                                                            T* __restrict__ C, int ldc) {
+// The tile body.  TB: B is given transposed (element (k, j) at B[j + k*ldb]),
+// as in the symmetric update A22 -= L21 L21^T where both operands are the
+// same column block.  LOW: only C's lower triangle is updated -- element
+// (i, j) of C when i + diag >= j -- tiles wholly above it are skipped and
+// tiles across it store only their lower part.
+template <typename T, int BK, bool TB, bool LOW>
+__device__ __forceinline__ void gemm_tile(int M, int N, int K, const T* __restrict__ A, int lda,
+                                          const T* __restrict__ B, int ldb, T* __restrict__ C, int ldc,
+                                          int diag) {
     typedef typename Acc<T>::type V4;
     constexpr int PA = 2, PB = 1;
     __shared__ T As[2][BK][kBM + PA];
@@ -59,6 +64,9 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_nn_sub(int M, int N, int K, 
     int tm, tn;
     tile_of(tiles_m, tiles_n, tm, tn);
     const int m0 = tm * kBM, n0 = tn * kBN;
+    if constexpr (LOW) {
+        if (m0 + kBM - 1 + diag < n0) return;          // the whole tile lies above the diagonal
+    }
     const int tid = threadIdx.x;
     const int wave = tid / 64, lane = tid % 64;
     const int l16 = lane % 16, lg = lane / 16;
@@ -67,7 +75,10 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_nn_sub(int M, int N, int K, 
     // Tiles inside the matrix (all but the last tile row and column) take a
     // branch-free path: no per-element bounds checks, B read two k at a time.
     const bool interior = m0 + kBM <= M && n0 + kBN <= N;
-    const bool vecb = interior && (reinterpret_cast<unsigned long long>(B) % (2 * sizeof(T))) == 0 && (ldb % 2) == 0;
+    const bool vecb = !TB && interior && (reinterpret_cast<unsigned long long>(B) % (2 * sizeof(T))) == 0 &&
+                      (ldb % 2) == 0;
+    // LOW: tiles wholly below the diagonal store everything
+    const bool full = !LOW || m0 + diag >= n0 + kBN - 1;
 
     // accumulators start from C
     V4 acc[4][4];
@@ -93,6 +104,8 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_nn_sub(int M, int N, int K, 
     constexpr int AKS = kThreads / kBM;
     const int b_col = tid / (kThreads / kBN), b_kh = tid % (kThreads / kBN);   // B: k contiguous
     constexpr int BKS = BK / (kThreads / kBN);
+    const int t_col = tid % kBN, t_k0 = tid / kBN;                               // B^T: j contiguous
+    constexpr int TKS = kThreads / kBN;
 
     static_assert(BKS % 2 == 0, "B is read two k at a time");
     typedef T T2 __attribute__((ext_vector_type(2)));
@@ -100,6 +113,11 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_nn_sub(int M, int N, int K, 
         if (interior && k0 + BK <= K) {
 #pragma unroll
             for (int r = 0; r < AL; ++r) ra[r] = A[m0 + a_row + (long long)(k0 + a_k0 + AKS * r) * lda];
+            if constexpr (TB) {
+#pragma unroll
+                for (int e = 0; e < BL; ++e) rbv[e] = B[n0 + t_col + (long long)(k0 + t_k0 + TKS * e) * ldb];
+                return;
+            }
             const T* bp = B + k0 + b_kh * BKS + (long long)(n0 + b_col) * ldb;
             if (vecb) {
 #pragma unroll
@@ -122,16 +140,24 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_nn_sub(int M, int N, int K, 
         }
 #pragma unroll
         for (int e = 0; e < BL; ++e) {
-            const int kk = b_kh * BKS + e;
-            const int gc = n0 + b_col, gk = k0 + kk;
-            rbv[e] = (gc < N && gk < K) ? B[gk + (long long)gc * ldb] : T(0);
+            if constexpr (TB) {
+                const int gc = n0 + t_col, gk = k0 + t_k0 + TKS * e;
+                rbv[e] = (gc < N && gk < K) ? B[gc + (long long)gk * ldb] : T(0);
+            } else {
+                const int kk = b_kh * BKS + e;
+                const int gc = n0 + b_col, gk = k0 + kk;
+                rbv[e] = (gc < N && gk < K) ? B[gk + (long long)gc * ldb] : T(0);
+            }
         }
     };
     auto store = [&](int buf) {
 #pragma unroll
         for (int r = 0; r < AL; ++r) As[buf][a_k0 + AKS * r][a_row] = -ra[r];
 #pragma unroll
-        for (int e = 0; e < BL; ++e) Bs[buf][b_col][b_kh * BKS + e] = rbv[e];
+        for (int e = 0; e < BL; ++e) {
+            if constexpr (TB) Bs[buf][t_col][t_k0 + TKS * e] = rbv[e];
+            else Bs[buf][b_col][b_kh * BKS + e] = rbv[e];
+        }
     };
 
     const int nk = (K + BK - 1) / BK;
@@ -166,11 +192,28 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_nn_sub(int M, int N, int K, 
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int col = n0 + wn * 64 + cb * 16 + Acc<T>::col(lg, r);
-                    if (interior || col < N) C[row + (long long)col * ldc] = acc[rb][cb][r];
+                    if ((interior || col < N) && (full || row + diag >= col))
+                        C[row + (long long)col * ldc] = acc[rb][cb][r];
                 }
             }
         }
     }
+}
+
+template <typename T, int BK>
+__global__ __launch_bounds__(kThreads, 2) void gemm_nn_sub(int M, int N, int K, const T* __restrict__ A,
+                                                            int lda, const T* __restrict__ B, int ldb,
+                                                            T* __restrict__ C, int ldc) {
+    gemm_tile<T, BK, false, false>(M, N, K, A, lda, B, ldb, C, ldc, 0);
+}
+
+// C -= A B^T on the lower triangle of C (the symmetric rank-k update of a
+// Cholesky step, B = A's rows of the column block being updated).
+template <typename T, int BK>
+__global__ __launch_bounds__(kThreads, 2) void syrk_ln_sub(int M, int N, int K, const T* __restrict__ A,
+                                                            int lda, const T* __restrict__ B, int ldb,
+                                                            T* __restrict__ C, int ldc, int diag) {
+    gemm_tile<T, BK, true, true>(M, N, K, A, lda, B, ldb, C, ldc, diag);
 }
 
 // Mixed precision: C (FP32) -= diag(rs) (Ah Bh) diag(cs), Ah = FP16/BF16 rows
@@ -343,6 +386,17 @@ int launch_gemm(int M, int N, int K, const T* A, int lda, const T* B, int ldb, T
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+template <typename T>
+int launch_syrk_lower(int M, int N, int K, const T* A, int lda, const T* B, int ldb, T* C, int ldc, int diag,
+                      hipStream_t stream) {
+    if (M <= 0 || N <= 0 || K <= 0) return 0;
+    const long long tiles = (long long)((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
+    if (tiles > 0x7fffffffLL) return -1;
+    hipLaunchKernelGGL((syrk_ln_sub<T, 16>), dim3((unsigned)tiles), dim3(kThreads), 0, stream, M, N, K, A, lda,
+                       B, ldb, C, ldc, diag);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
 template <typename H>
 int launch_gemm_half(int M, int N, int K, const H* Ah, int lda_h, const H* Bh, int ldb_h,
                      const float* rs, const float* cs, float* C, int ldc, hipStream_t stream) {
@@ -356,6 +410,8 @@ int launch_gemm_half(int M, int N, int K, const H* Ah, int lda_h, const H* Bh, i
 template int launch_gemm<double>(int, int, int, const double*, int, const double*, int, double*, int,
                                  hipStream_t);
 template int launch_gemm<float>(int, int, int, const float*, int, const float*, int, float*, int, hipStream_t);
+template int launch_syrk_lower<double>(int, int, int, const double*, int, const double*, int, double*, int, int,
+                                       hipStream_t);
 template int launch_gemm_half<_Float16>(int, int, int, const _Float16*, int, const _Float16*, int,
                                         const float*, const float*, float*, int, hipStream_t);
 template int launch_gemm_half<__bf16>(int, int, int, const __bf16*, int, const __bf16*, int, const float*,

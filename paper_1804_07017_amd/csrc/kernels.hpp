@@ -80,6 +80,28 @@ int launch_gemm_half(int M, int N, int K, const H* Ah, int lda_h, const H* Bh, i
                      const float* cs, float* C, int ldc, hipStream_t stream);
 int launch_probe_mfma_f64(double* out, hipStream_t stream);
 
+// Symmetric update C -= A B^T on C's lower triangle (element (i,j) when
+// i + diag >= j); B is given transposed, element (k, j) at B[j + k*ldb].
+template <typename T>
+int launch_syrk_lower(int M, int N, int K, const T* A, int lda, const T* B, int ldb, T* C, int ldc, int diag,
+                      hipStream_t stream);
+
+// Cholesky panel (chol.hip): the m x w column block at A (its diagonal at
+// A[0]), lower triangle, w <= 512; persistent multi-work-group launch.
+template <typename T>
+struct CholPanelArgs {
+    T* A;
+    long long lda;
+    int m, w;
+    int* info;             // device; first non-positive pivot (1-based), set once
+    int info_col_base;     // global column of the panel's first column
+    unsigned* sync;        // [counter, error] of this launch's barrier
+    unsigned* sync_next;   // counter the next launch will use (cleared here)
+    long long spin_limit;  // wall-clock ticks a barrier may wait
+};
+template <typename T>
+int launch_chol_panel(const CholPanelArgs<T>& args, int wgs, hipStream_t stream);
+
 // ---- solves and refinement (solve.hip) ----
 // x (n x nrhs, ld) <- P x using per-chunk moves from launch_chunk_moves
 template <typename T>

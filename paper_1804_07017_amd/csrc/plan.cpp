@@ -88,7 +88,7 @@ int build_plan(int n, int b, int depth, std::vector<PlanTask>& out) {
     return build_plan(n, panel_starts(n, b, 0, 0), depth, out);
 }
 
-int build_plan(int n, const std::vector<int>& starts, int depth, std::vector<PlanTask>& out) {
+int build_plan(int n, const std::vector<int>& starts, int depth, std::vector<PlanTask>& out, bool lswap) {
     out.clear();
     if (n < 0) return -1;
     if (depth < 0 || depth > 2) return -3;
@@ -112,7 +112,7 @@ int build_plan(int n, const std::vector<int>& starts, int depth, std::vector<Pla
             panel_cols(k, c0, c1);
             push(kTaskPanel, k, c0, c1, 0);
             push(kTaskUpdate, k, c1, n, 0);
-            if (k >= 1) push(kTaskLswap, k, 0, c0, 0);
+            if (k >= 1 && lswap) push(kTaskLswap, k, 0, c0, 0);
         }
     } else {
         const int d = depth;
@@ -133,7 +133,7 @@ int build_plan(int n, const std::vector<int>& starts, int depth, std::vector<Pla
                 for (int i = k + 1; i < j; ++i) push(kTaskUpdate, i, c0, c1, 1);
                 push(kTaskPanel, j, c0, c1, 1);
             }
-            if (k >= 1) push(kTaskLswap, k, 0, starts[k], 2);
+            if (k >= 1 && lswap) push(kTaskLswap, k, 0, starts[k], 2);
         }
     }
     // Derive cross-stream waits from data accesses.

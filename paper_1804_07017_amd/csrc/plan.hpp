@@ -23,6 +23,7 @@ std::vector<int> panel_starts(int n, int b, int taper, int prec);
 int taper_width(int prec, int trailing);
 
 int build_plan(int n, int b, int depth, std::vector<PlanTask>& out);
-int build_plan(int n, const std::vector<int>& starts, int depth, std::vector<PlanTask>& out);
+// lswap = false: no LSWAP tasks (a factorization without row interchanges)
+int build_plan(int n, const std::vector<int>& starts, int depth, std::vector<PlanTask>& out, bool lswap = true);
 
 }  // namespace lu

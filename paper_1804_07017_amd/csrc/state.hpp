@@ -59,6 +59,7 @@ struct DeviceState {
 };
 
 DeviceState* device_state(int* err);
+int ensure_events(DeviceState* s, size_t count);   // grow the event ring to at least count
 void release_all();
 int panel_wgs_for(const DeviceState& s, int m, int panel_cus, bool wide = false);
 
