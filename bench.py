@@ -59,6 +59,64 @@ def gemm_algorithmic_bytes(lu, n, b, depth, taper):
     return tot / max(cnt, 1)
 
 
+def device_spd(lu, n, seed):
+    """SPD workload on the device: the symmetric part (B + B^T)/2 of a
+    uniform[-1,1) matrix B with each diagonal entry set to its row's absolute
+    sum (strictly diagonally dominant)."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    A = lu.colmajor(n)
+    A.uniform_(-1.0, 1.0, generator=g)
+    for c0 in range(0, n, 4096):
+        c1 = min(n, c0 + 4096)
+        sym = (A[c0:c1, :].clone() + A[:, c0:c1].t()) / 2.0
+        A[c0:c1, :] = sym
+        A[:, c0:c1] = sym.t()
+    A.diagonal().copy_(A.abs().sum(dim=1))
+    return A
+
+
+def cholesky_leg(lu, n, reps):
+    """FP64 Cholesky with look-ahead (chol_factor, default schedule) on the SPD
+    workload: median over reps timed factorizations after one warm-up, HIP
+    events on the factorization's stream; the pristine matrix is restored
+    before each run outside the timed region."""
+    import torch
+    A0 = device_spd(lu, n, 7)
+    A = lu.colmajor(n)
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()             # the input is built on the default stream
+    ts = []
+    for r in range(reps + 1):
+        with torch.cuda.stream(stream):
+            A.copy_(A0)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            rc = lu.chol_factor(A, stream=stream)
+            e1.record(stream)
+        stream.synchronize()
+        if rc != 0:
+            raise RuntimeError("chol_factor returned %d" % rc)
+        st, info = lu.lu_factor_info()
+        if r:
+            ts.append(e0.elapsed_time(e1))
+        print("bench: cholesky run %d %.1f ms status %d info %d" % (r, e0.elapsed_time(e1), st, info),
+              file=sys.stderr, flush=True)
+        if st != 0 or info != 0:
+            raise RuntimeError("cholesky: status %d info %d" % (st, info))
+    t = statistics.median(ts)
+    gf = n ** 3 / 3.0 / (t * 1e-3) / 1e9
+    del A0, A
+    torch.cuda.empty_cache()
+    return {"workload": "FP64 Cholesky with look-ahead of an SPD n=%d matrix (symmetric uniform[-1,1) part, "
+                        "diagonal = row absolute sum)" % n,
+            "schedule": {"b": 256, "depth": 2, "panel_cus": 32}, "t_factor_ms": round(t, 3),
+            "gflops": round(gf, 1), "flops": "n^3/3", "pct_fp64_peak": round(100 * gf / 1e3 / FP64_PEAK_TFLOPS, 2),
+            "runs": reps}
+
+
 def cpu_baseline(budget_s=20.0):
     """Time the CPU oracle on a bounded sample of the same workload: one
     factorization of a smaller uniform[-1,1) matrix, sized by cubic
@@ -92,6 +150,7 @@ def main():
     ap.add_argument("--taper", type=int, default=0, help="panel taper: 1 on, -1 off, 0 library default")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ir", action="store_true")
+    ap.add_argument("--no-chol", action="store_true", help="skip the Cholesky measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the hot path is built and measured on a single MI355X); "
@@ -231,6 +290,8 @@ def main():
                            "launches": gemm_launches,
                            "avg_launch_us": round(gemm_ms * 1e3 / gemm_launches, 2),
                            "avg_launch_gflop": round(gemm_flops / gemm_launches / 1e9, 3)}
+    if not args.no_chol:
+        out["cholesky"] = cholesky_leg(lu, n, args.steps)
     if not args.no_cpu_baseline:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

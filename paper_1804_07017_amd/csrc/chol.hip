@@ -7,7 +7,8 @@
 //
 // One persistent launch of P work-groups (256 threads each) factors the m x w
 // panel (rows relative to the panel's diagonal, m >= w), in blocks of 16
-// columns.  Thread t of work-group g owns panel rows g*256 + t + s*256*P.
+// columns.  Thread t of work-group g owns panel rows g*256 + t + s*256*P
+// (s < 4: the launch has at least m / 1024 work-groups).
 // For each block [cb, cb+16):
 //   every work-group reads the block's 16 x 16 diagonal part and factors it in
 //   LDS (one wave; all groups compute the same values);
@@ -33,11 +34,13 @@ namespace {
 constexpr int kCholThreads = 256;
 constexpr int kCholNB = 16;
 constexpr int kCholMaxW = 512;
+constexpr int kCholRows = 4;       // panel rows per thread (the launch has >= m / 1024 groups)
+constexpr int kChunk = 8;          // columns per pass of the in-panel update
 
 template <typename T>
 __global__ __launch_bounds__(kCholThreads) void chol_panel_kernel(CholPanelArgs<T> a) {
     __shared__ T D[kCholNB][kCholNB + 1];                  // the block's factored diagonal part
-    __shared__ T Ut[kCholMaxW - kCholNB][kCholNB + 1];     // L rows of the panel's diagonal region
+    __shared__ T UtT[kCholNB][kCholMaxW];                  // L rows of the panel's diagonal region, transposed
     __shared__ int s_bad;
     const int tid = threadIdx.x;
     const int g = blockIdx.x;
@@ -79,23 +82,44 @@ __global__ __launch_bounds__(kCholThreads) void chol_panel_kernel(CholPanelArgs<
             }
         }
         __syncthreads();
-        // 2. rows below the diagonal part: x <- x L_bb^-T
-        for (int i = cb + nbw + g * kCholThreads + tid; i < m; i += stride) {
-            T x[kCholNB];
+        // 2. rows below the diagonal part: x <- x L_bb^-T for all of this
+        //    thread's rows at once; the solved rows stay in registers as the
+        //    left operand of step 3
+        const int right0 = cb + nbw;
+        const int row0 = right0 + g * kCholThreads + tid;
+        T x[kCholRows][kCholNB];
 #pragma unroll
-            for (int c = 0; c < kCholNB; ++c) x[c] = (c < nbw) ? A[i + (long long)(cb + c) * lda] : T(0);
+        for (int r = 0; r < kCholRows; ++r) {
+            const int i = row0 + r * stride;
+            const int ic = min(i, m - 1);              // clamped: unconditional loads
 #pragma unroll
             for (int c = 0; c < kCholNB; ++c) {
-                if (c < nbw) {
-                    T v = x[c];
-#pragma unroll
-                    for (int k = 0; k < c; ++k) v = v - x[k] * D[c][k];
-                    x[c] = v / D[c][c];
-                }
+                const T v = A[ic + (long long)(cb + min(c, nbw - 1)) * lda];
+                x[r][c] = (i < m && c < nbw) ? v : T(0);
             }
+        }
 #pragma unroll
-            for (int c = 0; c < kCholNB; ++c)
-                if (c < nbw) A[i + (long long)(cb + c) * lda] = x[c];
+        for (int c = 0; c < kCholNB; ++c) {
+            if (c < nbw) {
+                const T dcc = D[c][c];
+#pragma unroll
+                for (int k = 0; k < c; ++k) {
+                    const T dck = D[c][k];
+#pragma unroll
+                    for (int r = 0; r < kCholRows; ++r) x[r][c] = x[r][c] - x[r][k] * dck;
+                }
+#pragma unroll
+                for (int r = 0; r < kCholRows; ++r) x[r][c] = x[r][c] / dcc;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kCholRows; ++r) {
+            const int i = row0 + r * stride;
+            if (i < m) {
+#pragma unroll
+                for (int c = 0; c < kCholNB; ++c)
+                    if (c < nbw) A[i + (long long)(cb + c) * lda] = x[r][c];
+            }
         }
         // every group has read the diagonal part (step 1) before group 0
         // overwrites it with the factor
@@ -107,25 +131,45 @@ __global__ __launch_bounds__(kCholThreads) void chol_panel_kernel(CholPanelArgs<
             }
             if (tid == 0 && s_bad != 0 && a.info) atomicCAS(a.info, 0, a.info_col_base + cb + s_bad);
         }
-        const int right0 = cb + nbw;
         if (right0 >= w) break;
-        // 3. the panel columns right of the block, lower triangle
-        for (int e = tid; e < (w - right0) * kCholNB; e += kCholThreads) {
-            const int c = e / kCholNB, k = e % kCholNB;
-            Ut[c][k] = (k < nbw) ? A[(right0 + c) + (long long)(cb + k) * lda] : T(0);
+        // 3. the panel columns right of the block, lower triangle, kChunk
+        //    columns at a time (every row's loads of a chunk in flight together)
+        {
+            const int wr = (w - right0 + kChunk - 1) / kChunk * kChunk;     // zero past w: whole chunks
+            for (int e = tid; e < wr * kCholNB; e += kCholThreads) {
+                const int c = e % wr, k = e / wr;
+                UtT[k][c] = (k < nbw && right0 + c < w) ? A[(right0 + c) + (long long)(cb + k) * lda] : T(0);
+            }
         }
         __syncthreads();
-        for (int i = right0 + g * kCholThreads + tid; i < m; i += stride) {
-            T l[kCholNB];
+        for (int c0 = right0; c0 < w; c0 += kChunk) {
+            T v[kCholRows][kChunk];
 #pragma unroll
-            for (int k = 0; k < kCholNB; ++k) l[k] = (k < nbw) ? A[i + (long long)(cb + k) * lda] : T(0);
-            const int cend = min(w, i + 1);
-            for (int c = right0; c < cend; ++c) {
-                T v = A[i + (long long)c * lda];
+            for (int r = 0; r < kCholRows; ++r) {
+                const int i = row0 + r * stride;
 #pragma unroll
-                for (int k = 0; k < kCholNB; ++k)
-                    if (k < nbw) v = v - l[k] * Ut[c - right0][k];
-                A[i + (long long)c * lda] = v;
+                for (int cc = 0; cc < kChunk; ++cc) {
+                    const int c = c0 + cc;
+                    v[r][cc] = (i < m && c < w && c <= i) ? A[i + (long long)c * lda] : T(0);
+                }
+            }
+#pragma unroll
+            for (int cc = 0; cc < kChunk; ++cc) {
+#pragma unroll
+                for (int k = 0; k < kCholNB; ++k) {
+                    const T u = UtT[k][c0 - right0 + cc];
+#pragma unroll
+                    for (int r = 0; r < kCholRows; ++r) v[r][cc] = v[r][cc] - x[r][k] * u;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < kCholRows; ++r) {
+                const int i = row0 + r * stride;
+#pragma unroll
+                for (int cc = 0; cc < kChunk; ++cc) {
+                    const int c = c0 + cc;
+                    if (i < m && c < w && c <= i) A[i + (long long)c * lda] = v[r][cc];
+                }
             }
         }
         if (grid_barrier(a.sync, a.sync + 1, ++epoch, a.spin_limit)) return;
@@ -137,6 +181,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_panel_kernel(CholPanelArgs<
 template <typename T>
 int launch_chol_panel(const CholPanelArgs<T>& args, int wgs, hipStream_t stream) {
     if (args.w < 1 || args.w > kCholMaxW || args.m < args.w || wgs < 1) return -1;
+    if ((long long)wgs * kCholThreads * kCholRows < args.m) return -1;   // rows per thread bound
     hipLaunchKernelGGL((chol_panel_kernel<T>), dim3(wgs), dim3(kCholThreads), 0, stream, args);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }

@@ -32,12 +32,17 @@ constexpr int kBM = 128, kBN = 128, kThreads = 256;
 // chunk of the tile order, and the order walks kGroupM tile-rows down before
 // moving to the next tile column, so that the A rows and B columns of the
 // tiles an XCD runs at the same time stay in its L2.
+//
+// A triangular update (LOW below) keeps the plain order instead: its empty
+// tiles sit at the top of the tile order, and dealing contiguous chunks to
+// the XCDs would leave the first XCDs nearly idle; in plain order every XCD
+// takes every 8th tile, a fair share of the full ones.
 constexpr int kGroupM = 8;
-__device__ __forceinline__ void tile_of(int tiles_m, int tiles_n, int& tm, int& tn) {
+__device__ __forceinline__ void tile_of(int tiles_m, int tiles_n, int& tm, int& tn, bool xcd_chunks = true) {
     const int nt = tiles_m * tiles_n;
     int bid = blockIdx.x;
     const int per = nt / 8;
-    if (per > 0 && bid < per * 8) bid = (bid % 8) * per + bid / 8;
+    if (xcd_chunks && per > 0 && bid < per * 8) bid = (bid % 8) * per + bid / 8;
     const int grp = kGroupM * tiles_n;
     const int gi = bid / grp, r = bid % grp;
     const int m0 = gi * kGroupM;
@@ -62,7 +67,7 @@ __device__ __forceinline__ void gemm_tile(int M, int N, int K, const T* __restri
 
     const int tiles_m = (M + kBM - 1) / kBM, tiles_n = (N + kBN - 1) / kBN;
     int tm, tn;
-    tile_of(tiles_m, tiles_n, tm, tn);
+    tile_of(tiles_m, tiles_n, tm, tn, !LOW);
     const int m0 = tm * kBM, n0 = tn * kBN;
     if constexpr (LOW) {
         if (m0 + kBM - 1 + diag < n0) return;          // the whole tile lies above the diagonal
