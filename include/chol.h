@@ -16,8 +16,9 @@
  *
  * Errors: 0 = enqueued; -1 n < 0, -2 A NULL with n > 0, -3 lda < max(1, n),
  * -4 invalid schedule (b not in {32,64,128,256,512}, depth not in {0,1,2},
- * panel_cus > 256); LU_ERR_* (lu.h) for HIP failures, workspace allocation
- * and panel-barrier time-outs.  A matrix that is not positive definite is not
+ * panel_cus > 256); LU_ERR_UNSUPPORTED for n > 65536 (the panel kernel holds
+ * at most 1024 rows per compute unit, on at most 64 units); LU_ERR_* (lu.h)
+ * for HIP failures, workspace allocation and panel-barrier time-outs.  A matrix that is not positive definite is not
  * an error of the call: as in LAPACK potrf, INFO = j > 0 names the first
  * column whose pivot was not positive (the values from that column on are
  * not a factorization).  INFO goes to d_info (device int, zeroed by the call)

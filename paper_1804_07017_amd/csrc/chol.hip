@@ -8,7 +8,7 @@
 // One persistent launch of P work-groups (256 threads each) factors the m x w
 // panel (rows relative to the panel's diagonal, m >= w), in blocks of 16
 // columns.  Thread t of work-group g owns panel rows g*256 + t + s*256*P
-// (s < 4: the launch has at least m / 1024 work-groups).
+// (s < ROWS, 2 or 4: the launch has at least m / (256 ROWS) work-groups).
 // For each block [cb, cb+16):
 //   every work-group reads the block's 16 x 16 diagonal part and factors it in
 //   LDS (one wave; all groups compute the same values);
@@ -34,10 +34,9 @@ namespace {
 constexpr int kCholThreads = 256;
 constexpr int kCholNB = 16;
 constexpr int kCholMaxW = 512;
-constexpr int kCholRows = 4;       // panel rows per thread (the launch has >= m / 1024 groups)
-constexpr int kChunk = 8;          // columns per pass of the in-panel update
+constexpr int kChunkCols = 8;     // columns per pass of the in-panel update (wider passes spill)
 
-template <typename T>
+template <typename T, int kCholRows>
 __global__ __launch_bounds__(kCholThreads) void chol_panel_kernel(CholPanelArgs<T> a) {
     __shared__ T D[kCholNB][kCholNB + 1];                  // the block's factored diagonal part
     __shared__ T UtT[kCholNB][kCholMaxW];                  // L rows of the panel's diagonal region, transposed
@@ -51,6 +50,8 @@ __global__ __launch_bounds__(kCholThreads) void chol_panel_kernel(CholPanelArgs<
     unsigned epoch = 0;
     if (g == 0 && tid == 0 && a.sync_next) a.sync_next[0] = 0u;   // the next launch's barrier counter
     const int stride = kCholThreads * P;
+    constexpr int kChunk = kChunkCols;                      // columns per pass of the in-panel update
+    constexpr bool kPrefetch = kCholRows <= 2;              // registers for a second chunk
 
     for (int cb = 0; cb < w; cb += kCholNB) {
         const int nbw = min(kCholNB, w - cb);
@@ -142,8 +143,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_panel_kernel(CholPanelArgs<
             }
         }
         __syncthreads();
-        for (int c0 = right0; c0 < w; c0 += kChunk) {
-            T v[kCholRows][kChunk];
+        auto load_chunk = [&](int c0, T (&v)[kCholRows][kChunk]) {
 #pragma unroll
             for (int r = 0; r < kCholRows; ++r) {
                 const int i = row0 + r * stride;
@@ -153,6 +153,13 @@ __global__ __launch_bounds__(kCholThreads) void chol_panel_kernel(CholPanelArgs<
                     v[r][cc] = (i < m && c < w && c <= i) ? A[i + (long long)c * lda] : T(0);
                 }
             }
+        };
+        // the next chunk's loads are issued before this chunk's arithmetic
+        T v[kCholRows][kChunk];
+        load_chunk(right0, v);
+        for (int c0 = right0; c0 < w; c0 += kChunk) {
+            T vn[kCholRows][kChunk];
+            if (kPrefetch && c0 + kChunk < w) load_chunk(c0 + kChunk, vn);
 #pragma unroll
             for (int cc = 0; cc < kChunk; ++cc) {
 #pragma unroll
@@ -171,6 +178,13 @@ __global__ __launch_bounds__(kCholThreads) void chol_panel_kernel(CholPanelArgs<
                     if (i < m && c < w && c <= i) A[i + (long long)c * lda] = v[r][cc];
                 }
             }
+            if (c0 + kChunk < w) {
+                if (!kPrefetch) load_chunk(c0 + kChunk, vn);
+#pragma unroll
+                for (int r = 0; r < kCholRows; ++r)
+#pragma unroll
+                    for (int cc = 0; cc < kChunk; ++cc) v[r][cc] = vn[r][cc];
+            }
         }
         if (grid_barrier(a.sync, a.sync + 1, ++epoch, a.spin_limit)) return;
     }
@@ -181,8 +195,13 @@ __global__ __launch_bounds__(kCholThreads) void chol_panel_kernel(CholPanelArgs<
 template <typename T>
 int launch_chol_panel(const CholPanelArgs<T>& args, int wgs, hipStream_t stream) {
     if (args.w < 1 || args.w > kCholMaxW || args.m < args.w || wgs < 1) return -1;
-    if ((long long)wgs * kCholThreads * kCholRows < args.m) return -1;   // rows per thread bound
-    hipLaunchKernelGGL((chol_panel_kernel<T>), dim3(wgs), dim3(kCholThreads), 0, stream, args);
+    const long long per = (long long)wgs * kCholThreads;     // rows per thread-slot sweep
+    if (per * 2 >= args.m)
+        hipLaunchKernelGGL((chol_panel_kernel<T, 2>), dim3(wgs), dim3(kCholThreads), 0, stream, args);
+    else if (per * 4 >= args.m)
+        hipLaunchKernelGGL((chol_panel_kernel<T, 4>), dim3(wgs), dim3(kCholThreads), 0, stream, args);
+    else
+        return -1;                                            // more than 4 rows per thread
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 

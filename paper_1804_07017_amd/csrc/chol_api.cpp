@@ -61,11 +61,13 @@ int chol_execute(DeviceState* s, int n, double* A, long long lda, int* info, int
             pa.sync_next = s->sync + 2 * (1 - s->sync_slot);
             s->sync_slot = 1 - s->sync_slot;
             pa.spin_limit = s->spin_limit;
-            // one group per 1024 panel rows, at least the panel CU share, at
-            // most 64 and the CU count (every group must be resident at once)
-            int wgs = std::max((pa.m + 1023) / 1024, std::max(1, panel_cus));
+            // one group per 512 panel rows (two per thread), at least the panel
+            // CU share, at most 64 and the CU count (every group must be
+            // resident at once); past 64 x 512 rows, four rows per thread
+            int wgs = std::max((pa.m + 511) / 512, std::max(1, panel_cus));
             wgs = std::min(wgs, std::min(64, s->num_cus));
             wgs = std::min(wgs, std::max(1, (pa.m + 255) / 256));
+            if ((long long)wgs * 1024 < pa.m) return LU_ERR_UNSUPPORTED;   // > 4 rows per thread
             if (launch_chol_panel<double>(pa, wgs, st)) return LU_ERR_HIP;
         } else if (t.kind == kTaskUpdate) {
             const int c0 = t.col_begin, c1 = t.col_end;
@@ -109,6 +111,7 @@ int chol_factor_impl(int n, double* A, int lda, const lu_schedule_t* sched, int*
     int err;
     DeviceState* s = device_state(&err);
     if (!s) return err;
+    if ((long long)n > 1024LL * std::min(64, s->num_cus)) return LU_ERR_UNSUPPORTED;
     int* info = d_info ? d_info : s->info;
     if (launch_fill_zero(info, sizeof(int), stream)) return LU_ERR_HIP;
     s->last_stream = stream;
