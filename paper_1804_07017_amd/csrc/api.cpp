@@ -106,6 +106,10 @@ DeviceState* device_state(int* err) {
     s->spin_limit = (long long)rate_khz * 1000ll * 2;   // 2 seconds
     s->panel_occupancy = 1;
     if (const char* e = std::getenv("LU_PANEL_OCC")) s->panel_occupancy = std::atoi(e) == 2 ? 2 : 1;
+    if (const char* e = std::getenv("LU_WIDE_ROWS")) {
+        const int v = std::atoi(e);
+        if (v > 0) s->wide_rows = v;
+    }
     if (const char* e = std::getenv("LU_DEBUG_BARRIER_SPIN")) {
         long long v = std::atoll(e);
         if (v > 0) s->spin_limit = v;                    // debug knob: tiny bound forces the timeout path
@@ -215,7 +219,6 @@ const DeviceState::Plan* get_plan(DeviceState* s, int n, const lu_schedule_t& sc
 // ---------------------------------------------------------------- executor
 struct HalfNone {};
 
-constexpr int kWidePanelRows = 20480;
 
 template <typename T>
 int run_panel(DeviceState* s, T* A, long long lda, int n, int j0, int w, int* ipiv, int* info, int* moves,
@@ -246,8 +249,8 @@ int run_panel(DeviceState* s, T* A, long long lda, int n, int j0, int w, int* ip
     pa.tag_base = (unsigned)s->panel_launches << 10;
     pa.spin_limit = s->spin_limit;
     pa.occupancy = s->panel_occupancy;
-    // tall FP64 panels (m > kWidePanelRows) use 4*threads rows per group
-    const bool wide = sizeof(T) == 8 && m > kWidePanelRows;
+    // tall FP64 panels (m > wide_rows) use 4*threads rows per group
+    const bool wide = sizeof(T) == 8 && m > s->wide_rows;
     int wgs = panel_wgs_for(*s, m, wgs_req, wide);
     if (wgs < 0) return LU_ERR_UNSUPPORTED;
     return launch_panel<T>(pa, wgs, st) == 0 ? 0 : LU_ERR_HIP;
