@@ -60,13 +60,29 @@ __global__ __launch_bounds__(kThreads) void trsv_lower_unit_kernel(const T* __re
     const int nb = min(kRB, n - r * kRB);
     // the diagonal block does not depend on other blocks: stage it first
     for (int s = g; s < kRB; s += 4) Ld[s][i] = (row < n && s < nb) ? LU[row + (long long)(r * kRB + s) * lda] : T(0);
+    // this thread's slice of block (r, cb) of L: loaded one block ahead, before
+    // the wait for block cb's x, so that only x is fetched once the flag is up
+    constexpr int kPerT = kRB / 4;
+    auto load_l = [&](int cb, T (&lv)[kPerT]) {
+        const int j0 = cb * kRB;
+#pragma unroll
+        for (int u = 0; u < kPerT; ++u) lv[u] = (row < n) ? LU[row + (long long)(j0 + g + 4 * u) * lda] : T(0);
+    };
     T acc = T(0);
+    T lv[kPerT];
+    if (r > 0) load_l(0, lv);
     for (int cb = 0; cb < r; ++cb) {
+        T ln[kPerT];
+        if (cb + 1 < r) load_l(cb + 1, ln);
         if (wait_flag(&flags[cb], epoch, err, limit)) return;
         if (row < n) {
             const int j0 = cb * kRB;
-#pragma unroll 4
-            for (int jj = g; jj < kRB; jj += 4) acc += LU[row + (long long)(j0 + jj) * lda] * xload(&x[j0 + jj]);
+#pragma unroll
+            for (int u = 0; u < kPerT; ++u) acc += lv[u] * xload(&x[j0 + g + 4 * u]);
+        }
+        if (cb + 1 < r) {
+#pragma unroll
+            for (int u = 0; u < kPerT; ++u) lv[u] = ln[u];
         }
     }
     part[g][i] = acc;
@@ -75,7 +91,7 @@ __global__ __launch_bounds__(kThreads) void trsv_lower_unit_kernel(const T* __re
     if (tid < kRB) {
         y = (row < n) ? x[row] - ((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) : T(0);
         for (int s = 0; s < nb; ++s) {
-            const T xs = __shfl(y, s, kWave);
+            const T xs = lane_t(y, s);                 // lane s's value (s is uniform)
             if (i > s) y -= Ld[s][i] * xs;
         }
     }
@@ -94,14 +110,34 @@ __global__ __launch_bounds__(kThreads) void trsv_upper_kernel(const T* __restric
     const int row = r * kRB + i;
     const int nb = min(kRB, n - r * kRB);
     for (int s = g; s < kRB; s += 4) Ud[s][i] = (row < n && s < nb) ? LU[row + (long long)(r * kRB + s) * lda] : T(0);
+    // block (r, cb) of U loaded one block ahead of the wait (as in the lower
+    // solve); columns past n (only in the last block) contribute zero
+    constexpr int kPerT = kRB / 4;
+    auto load_u = [&](int cb, T (&lv)[kPerT]) {
+        const int j0 = cb * kRB;
+#pragma unroll
+        for (int u = 0; u < kPerT; ++u) {
+            const int j = j0 + g + 4 * u;
+            lv[u] = (row < n && j < n) ? LU[row + (long long)j * lda] : T(0);
+        }
+    };
     T acc = T(0);
+    T lv[kPerT];
+    if (r < nblk - 1) load_u(nblk - 1, lv);
     for (int cb = nblk - 1; cb > r; --cb) {
+        T ln[kPerT];
+        if (cb - 1 > r) load_u(cb - 1, ln);
         if (wait_flag(&flags[cb], epoch, err, limit)) return;
         if (row < n) {
             const int j0 = cb * kRB;
             const int nj = min(kRB, n - j0);
-#pragma unroll 4
-            for (int jj = g; jj < nj; jj += 4) acc += LU[row + (long long)(j0 + jj) * lda] * xload(&x[j0 + jj]);
+#pragma unroll
+            for (int u = 0; u < kPerT; ++u)
+                if (g + 4 * u < nj) acc += lv[u] * xload(&x[j0 + g + 4 * u]);
+        }
+        if (cb - 1 > r) {
+#pragma unroll
+            for (int u = 0; u < kPerT; ++u) lv[u] = ln[u];
         }
     }
     part[g][i] = acc;
@@ -111,7 +147,7 @@ __global__ __launch_bounds__(kThreads) void trsv_upper_kernel(const T* __restric
         y = (row < n) ? x[row] - ((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) : T(0);
         for (int s = nb - 1; s >= 0; --s) {
             if (i == s) y = y / Ud[s][i];
-            const T xs = __shfl(y, s, kWave);
+            const T xs = lane_t(y, s);                 // lane s's value (s is uniform)
             if (i < s) y -= Ud[s][i] * xs;
         }
     }
