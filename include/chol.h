@@ -47,6 +47,15 @@ int chol_factor(int n, double* A, int lda, hipStream_t stream);
  * default); taper is ignored (every panel b wide, the last one ragged). */
 int chol_factor_ex(int n, double* A, int lda, const lu_schedule_t* sched, int* d_info, hipStream_t stream);
 
+/* Solve A X = B with the factor of chol_factor (LAPACK potrs, lower):
+ * B <- L^-T L^-1 B, nrhs columns, in place.  L and B are DEVICE pointers
+ * (column-major, lda, ldb >= max(1, n)); only L's lower triangle is read.
+ * Asynchronous on `stream`.  Errors: -1 n < 0, -2 nrhs < 0, -3 L NULL, -4 lda,
+ * -5 B NULL, -6 ldb; LU_ERR_* for HIP failures.  A wait between the solve's
+ * blocks that times out sets the library's solve error word and leaves B
+ * undefined. */
+int chol_solve(int n, int nrhs, const double* L, int lda, double* B, int ldb, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -60,6 +60,7 @@ _SIGS = {
     "lu_plan_build": (_I, [_I, _I, _I, ctypes.POINTER(PlanTask), _I]),
     "chol_factor": (_I, [_I, _P, _I, _P]),
     "chol_factor_ex": (_I, [_I, _P, _I, ctypes.POINTER(Schedule), _P, _P]),
+    "chol_solve": (_I, [_I, _I, _P, _I, _P, _I, _P]),
     "lu_plan_panels": (_I, [_I, _I, _I, _I, ctypes.POINTER(_I), _I]),
     "lu_plan_build_panels": (_I, [_I, ctypes.POINTER(_I), _I, _I, ctypes.POINTER(PlanTask), _I]),
     "lu_k_panel": (_I, [_I, _I, _I, _P, _I, _P, _I, _P, _P]),
@@ -181,6 +182,14 @@ def chol_factor(A, stream=None, n=None):
 def chol_factor_ex(A, sched=None, d_info=None, stream=None, n=None):
     n = A.shape[0] if n is None else n
     return load().chol_factor_ex(n, _ptr(A), _ld(A), _sched(sched), _ptr(d_info), _stream(stream))
+
+
+def chol_solve(L, B, stream=None, n=None):
+    """B <- (L L^T)^-1 B with the factor of chol_factor (device tensors, column-major)."""
+    n = L.shape[0] if n is None else n
+    nrhs = 1 if B.dim() == 1 else B.shape[1]
+    return load().chol_solve(n, nrhs, _ptr(L), _ld(L), _ptr(B), _ld(B) if B.dim() > 1 else max(1, n),
+                             _stream(stream))
 
 
 def lu_factor_info():

@@ -119,9 +119,45 @@ int chol_factor_impl(int n, double* A, int lda, const lu_schedule_t* sched, int*
     return chol_execute(s, n, A, lda, info, b, depth, panel_cus, stream);
 }
 
+int chol_solve_impl(int n, int nrhs, const double* L, int lda, double* B, int ldb, hipStream_t stream) {
+    int err;
+    DeviceState* s = device_state(&err);
+    if (!s) return err;
+    const int nblk = (n + 63) / 64;
+    int rc;
+    if (s->flags.bytes < (size_t)nblk * sizeof(int)) {
+        if ((rc = ensure(s->flags, (size_t)nblk * sizeof(int)))) return rc;
+        LU_HIP(hipMemset(s->flags.ptr, 0, s->flags.bytes));
+        s->trsv_epoch = 0;
+    }
+    int* flags = reinterpret_cast<int*>(s->flags.ptr);
+    unsigned* terr = s->sync + 4;                 // the triangular solves' error word
+    for (int c = 0; c < nrhs; ++c) {
+        if (s->trsv_epoch > 0x3ffffff0) {
+            if (launch_fill_zero(s->flags.ptr, s->flags.bytes, stream)) return LU_ERR_HIP;
+            s->trsv_epoch = 0;
+        }
+        const int e1 = ++s->trsv_epoch, e2 = ++s->trsv_epoch;
+        if (launch_trsv_chol<double>(L, lda, n, B + (long long)c * ldb, flags, e1, e2, terr, s->spin_limit, stream))
+            return LU_ERR_HIP;
+    }
+    return 0;
+}
+
 }  // namespace lu
 
 extern "C" {
+
+int chol_solve(int n, int nrhs, const double* L, int lda, double* B, int ldb, hipStream_t stream) {
+    if (n < 0) return -1;
+    if (nrhs < 0) return -2;
+    if (!L && n > 0) return -3;
+    if (lda < std::max(1, n)) return -4;
+    if (!B && n > 0 && nrhs > 0) return -5;
+    if (ldb < std::max(1, n)) return -6;
+    if (n == 0 || nrhs == 0) return 0;
+    return lu::chol_solve_impl(n, nrhs, L, lda, B, ldb, stream);
+}
 
 int chol_factor(int n, double* A, int lda, hipStream_t stream) {
     return lu::chol_factor_impl(n, A, lda, nullptr, nullptr, stream);

@@ -110,6 +110,11 @@ int launch_apply_chunk_moves(T* X, long long ldx, int n, int nrhs, int W, const 
 template <typename T>
 int launch_trsv_lower_unit(const T* LU, long long lda, int n, T* x, int* flags, int epoch, unsigned* err,
                            long long spin_limit, hipStream_t stream);
+// Cholesky solve of one right-hand side in place: L y = x, then L^T x = y
+// (L lower with its diagonal, column-major); one flag epoch per triangle.
+template <typename T>
+int launch_trsv_chol(const T* L, long long lda, int n, T* x, int* flags, int epoch_lower, int epoch_upper,
+                     unsigned* err, long long spin_limit, hipStream_t stream);
 template <typename T>
 int launch_trsv_upper(const T* LU, long long lda, int n, T* x, int* flags, int epoch, unsigned* err,
                       long long spin_limit, hipStream_t stream);

@@ -154,6 +154,122 @@ __global__ __launch_bounds__(kThreads) void trsv_upper_kernel(const T* __restric
     publish(x, row, y, tid < kRB && row < n, &flags[r], epoch);
 }
 
+// Solves with a Cholesky factor (L lower, non-unit diagonal, A = L L^T).
+// L y = b: as trsv_lower_unit_kernel with the division by the diagonal.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void trsv_chol_lower_kernel(const T* __restrict__ L, long long lda, int n,
+                                                                    T* __restrict__ x, int* flags, int epoch,
+                                                                    unsigned* err, long long limit) {
+    __shared__ T part[4][kRB];
+    __shared__ T Ld[kRB][kRB + 1];
+    const int r = blockIdx.x;
+    const int tid = threadIdx.x, i = tid % kRB, g = tid / kRB;
+    const int row = r * kRB + i;
+    const int nb = min(kRB, n - r * kRB);
+    for (int s = g; s < kRB; s += 4) Ld[s][i] = (row < n && s < nb) ? L[row + (long long)(r * kRB + s) * lda] : T(0);
+    constexpr int kPerT = kRB / 4;
+    auto load_l = [&](int cb, T (&lv)[kPerT]) {
+        const int j0 = cb * kRB;
+#pragma unroll
+        for (int u = 0; u < kPerT; ++u) lv[u] = (row < n) ? L[row + (long long)(j0 + g + 4 * u) * lda] : T(0);
+    };
+    T acc = T(0);
+    T lv[kPerT];
+    if (r > 0) load_l(0, lv);
+    for (int cb = 0; cb < r; ++cb) {
+        T ln[kPerT];
+        if (cb + 1 < r) load_l(cb + 1, ln);
+        if (wait_flag(&flags[cb], epoch, err, limit)) return;
+        if (row < n) {
+            const int j0 = cb * kRB;
+#pragma unroll
+            for (int u = 0; u < kPerT; ++u) acc += lv[u] * xload(&x[j0 + g + 4 * u]);
+        }
+        if (cb + 1 < r) {
+#pragma unroll
+            for (int u = 0; u < kPerT; ++u) lv[u] = ln[u];
+        }
+    }
+    part[g][i] = acc;
+    __syncthreads();
+    T y = T(0);
+    if (tid < kRB) {
+        y = (row < n) ? x[row] - ((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) : T(0);
+        for (int s = 0; s < nb; ++s) {
+            if (i == s) y = y / Ld[s][i];
+            const T xs = lane_t(y, s);                 // lane s's value (s is uniform)
+            if (i > s) y -= Ld[s][i] * xs;
+        }
+    }
+    publish(x, row, y, tid < kRB && row < n, &flags[r], epoch);
+}
+
+// L^T x = y, bottom block first.  Element (i, j) of L^T is L[j + i*lda]: the
+// off-diagonal blocks are read along j (contiguous) into LDS, transposed.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void trsv_chol_upper_kernel(const T* __restrict__ L, long long lda, int n,
+                                                                    T* __restrict__ x, int* flags, int epoch,
+                                                                    unsigned* err, long long limit) {
+    __shared__ T part[4][kRB];
+    __shared__ T Ud[kRB][kRB + 1];       // Ud[s][i] = L^T(i, s) = L(s, i), this block's diagonal part
+    __shared__ T S[kRB][kRB + 1];        // S[i][jj] = L^T(i, j0 + jj) of the block being applied
+    const int nblk = (n + kRB - 1) / kRB;
+    const int r = nblk - 1 - (int)blockIdx.x;
+    const int tid = threadIdx.x, i = tid % kRB, g = tid / kRB;
+    const int r0 = r * kRB;
+    const int row = r0 + i;
+    const int nb = min(kRB, n - r0);
+    // coalesced along the rows of L: thread (jj = tid % 64) reads L(r0 + jj, r0 + ii)
+    for (int ii = g; ii < kRB; ii += 4) {
+        const bool ok = i < nb && ii < nb && i >= ii;
+        Ud[i][ii] = ok ? L[(r0 + i) + (long long)(r0 + ii) * lda] : T(0);
+    }
+    constexpr int kPerT = kRB / 4;
+    auto load_s = [&](int cb, T (&v)[kPerT]) {   // v[u] = L(j0 + i, r0 + g + 4u): row j0+i of L
+        const int j0 = cb * kRB;
+#pragma unroll
+        for (int u = 0; u < kPerT; ++u) {
+            const int ii = g + 4 * u;
+            v[u] = (j0 + i < n && ii < nb) ? L[(j0 + i) + (long long)(r0 + ii) * lda] : T(0);
+        }
+    };
+    T acc = T(0);
+    T sv[kPerT];
+    if (r < nblk - 1) load_s(nblk - 1, sv);
+    for (int cb = nblk - 1; cb > r; --cb) {
+        T sn[kPerT];
+        if (cb - 1 > r) load_s(cb - 1, sn);
+        if (wait_flag(&flags[cb], epoch, err, limit)) return;
+#pragma unroll
+        for (int u = 0; u < kPerT; ++u) S[g + 4 * u][i] = sv[u];   // S[ii][jj]: row ii of L^T's block
+        __syncthreads();
+        if (row < n) {
+            const int j0 = cb * kRB;
+            const int nj = min(kRB, n - j0);
+#pragma unroll
+            for (int u = 0; u < kPerT; ++u)
+                if (g + 4 * u < nj) acc += S[i][g + 4 * u] * xload(&x[j0 + g + 4 * u]);
+        }
+        __syncthreads();
+        if (cb - 1 > r) {
+#pragma unroll
+            for (int u = 0; u < kPerT; ++u) sv[u] = sn[u];
+        }
+    }
+    part[g][i] = acc;
+    __syncthreads();
+    T y = T(0);
+    if (tid < kRB) {
+        y = (row < n) ? x[row] - ((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) : T(0);
+        for (int s = nb - 1; s >= 0; --s) {
+            if (i == s) y = y / Ud[s][i];
+            const T xs = lane_t(y, s);
+            if (i < s) y -= Ud[s][i] * xs;
+        }
+    }
+    publish(x, row, y, tid < kRB && row < n, &flags[r], epoch);
+}
+
 // P x for each right-hand side: chunk c's interchanges, chunks in order.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void apply_chunk_moves_kernel(T* X, long long ldx, int n, int W,
@@ -312,6 +428,18 @@ int launch_trsv_lower_unit(const T* LU, long long lda, int n, T* x, int* flags, 
 }
 
 template <typename T>
+int launch_trsv_chol(const T* L, long long lda, int n, T* x, int* flags, int epoch_lower, int epoch_upper,
+                     unsigned* err, long long spin_limit, hipStream_t stream) {
+    if (n <= 0) return 0;
+    const int nblk = (n + kRB - 1) / kRB;
+    hipLaunchKernelGGL((trsv_chol_lower_kernel<T>), dim3(nblk), dim3(kThreads), 0, stream, L, lda, n, x, flags,
+                       epoch_lower, err, spin_limit);
+    hipLaunchKernelGGL((trsv_chol_upper_kernel<T>), dim3(nblk), dim3(kThreads), 0, stream, L, lda, n, x, flags,
+                       epoch_upper, err, spin_limit);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <typename T>
 int launch_trsv_upper(const T* LU, long long lda, int n, T* x, int* flags, int epoch, unsigned* err,
                       long long spin_limit, hipStream_t stream) {
     if (n <= 0) return 0;
@@ -381,6 +509,8 @@ template int launch_trsv_lower_unit<double>(const double*, long long, int, doubl
                                             hipStream_t);
 template int launch_trsv_lower_unit<float>(const float*, long long, int, float*, int*, int, unsigned*, long long,
                                            hipStream_t);
+template int launch_trsv_chol<double>(const double*, long long, int, double*, int*, int, int, unsigned*, long long,
+                                      hipStream_t);
 template int launch_trsv_upper<double>(const double*, long long, int, double*, int*, int, unsigned*, long long,
                                        hipStream_t);
 template int launch_trsv_upper<float>(const float*, long long, int, float*, int*, int, unsigned*, long long,

@@ -64,6 +64,40 @@ def test_not_positive_definite_info(gpu, bad):
     assert info == oinfo
 
 
+@pytest.mark.parametrize("n,nrhs,lda,ldb", [(1, 1, None, None), (37, 2, 40, 41), (1000, 1, None, None),
+                                            (1500, 3, 1503, 1500)])
+def test_chol_solve_matches_oracle(gpu, n, nrhs, lda, ldb):
+    import torch
+    from scipy.linalg import solve_triangular
+    A = synth.spd(n, seed=n + 3)
+    B = synth.rhs(n, seed=n + 3, nrhs=nrhs)
+    dA = gpu.to_device(A, lda=lda)
+    assert gpu.chol_factor_ex(dA, sched=(128, 2, 16)) == 0
+    dB = gpu.to_device(B, lda=ldb)
+    assert gpu.chol_solve(dA, dB) == 0
+    torch.cuda.synchronize()
+    X = gpu.to_host(dB)
+    oF, _ = oracle.potrf(A)
+    oL = np.tril(oF)
+    Xo = solve_triangular(oL.T, solve_triangular(oL, B, lower=True), lower=False)
+    assert np.abs(X - Xo).max() <= 1e-10 * max(1.0, np.abs(Xo).max())
+    for c in range(nrhs):
+        assert oracle.r_hpl(A, X[:, c], B[:, c]) <= 16.0
+
+
+def test_chol_solve_argument_errors(gpu):
+    dA = gpu.to_device(np.eye(4, order="F"))
+    lib = gpu.load()
+    p = dA.data_ptr()
+    assert lib.chol_solve(-1, 1, p, 4, p, 4, None) == -1
+    assert lib.chol_solve(4, -1, p, 4, p, 4, None) == -2
+    assert lib.chol_solve(4, 1, None, 4, p, 4, None) == -3
+    assert lib.chol_solve(4, 1, p, 3, p, 4, None) == -4
+    assert lib.chol_solve(4, 1, p, 4, None, 4, None) == -5
+    assert lib.chol_solve(4, 1, p, 4, p, 3, None) == -6
+    assert lib.chol_solve(0, 1, None, 1, None, 1, None) == 0
+
+
 def test_zero_matrix_info(gpu):
     _, info = _chol(gpu, np.zeros((100, 100), order="F"), 32, 1)
     assert info == 1
@@ -137,3 +171,14 @@ def test_chol_32768_residual(gpu):
     nA = float((torch.tril(A0) ** 2).sum().item()) ** 0.5
     rf = acc ** 0.5 / (nA * n * 2.0 ** -53)
     assert rf <= 16.0, rf
+    del L
+    # solve with the factor: HPL residual of A x = b with A applied by a library GEMV
+    g = torch.Generator(device="cuda")
+    g.manual_seed(8)
+    b = torch.empty(n, dtype=torch.float64, device="cuda").uniform_(-1.0, 1.0, generator=g)
+    x = b.clone()
+    assert gpu.chol_solve(F, x) == 0
+    torch.cuda.synchronize()
+    r = (A0 @ x - b).abs().max().item()
+    hpl = r / (2.0 ** -53 * (A0.abs().sum(dim=1).max().item() * x.abs().max().item() + b.abs().max().item()) * n)
+    assert hpl <= 16.0, hpl
