@@ -20,6 +20,9 @@ Contents
   A = L L^T of the lower triangle, one column at a time (the unblocked form of
   a factorization that fits the blocked skeleton of Sec. 3.1); ``r_chol``:
   scaled residual ||A - L L^T||_F / (||A||_F n eps).
+* ``geqrf``: ctypes wrapper over ``qr_oracle.c`` -- plain FP64 Householder QR
+  (geqr2 storage: R on and above the diagonal, reflectors below, tau);
+  ``q_from`` builds Q explicitly from the reflectors.
 * ``mlp``: FP64 forward/backward/Adam of the schedule-selector network.
 """
 from __future__ import annotations
@@ -32,7 +35,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lu_oracle.c")
-_SRCS = [_SRC, os.path.join(_HERE, "chol_oracle.c")]
+_SRCS = [_SRC, os.path.join(_HERE, "chol_oracle.c"), os.path.join(_HERE, "qr_oracle.c")]
 _LIB = os.path.join(_HERE, "liblu_oracle.so")
 
 EPS64 = 2.0 ** -53
@@ -63,6 +66,9 @@ def _load():
         lib.oracle_getrs.restype = ctypes.c_int
         lib.oracle_getrs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+        lib.oracle_geqrf.restype = ctypes.c_int
+        lib.oracle_geqrf.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                     ctypes.c_int]
         lib.oracle_potrf.restype = ctypes.c_int
         lib.oracle_potrf.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
         _lib = lib
@@ -121,6 +127,30 @@ def potrf(A: np.ndarray, nthreads: int = 1):
     if info < 0:
         raise ValueError("oracle_potrf: illegal argument %d" % -info)
     return F, info
+
+
+def geqrf(A: np.ndarray, nthreads: int = 1):
+    """Householder QR of the m x n (m >= n) matrix A: returns (F, tau)."""
+    m, n = A.shape
+    F = np.array(A, dtype=np.float64, order="F", copy=True)
+    F, lda = _as_colmajor(F)
+    tau = np.zeros(max(n, 1), dtype=np.float64)
+    rc = _load().oracle_geqrf(m, n, F.ctypes.data, max(lda, 1), tau.ctypes.data, int(nthreads))
+    if rc < 0:
+        raise ValueError("oracle_geqrf: illegal argument %d" % -rc)
+    return F, tau[:n]
+
+
+def q_from(F: np.ndarray, tau: np.ndarray) -> np.ndarray:
+    """Q = H_0 H_1 ... H_{n-1}, H_j = I - tau_j v_j v_j^T (m x m), from geqrf's output."""
+    m, n = F.shape
+    Q = np.eye(m)
+    for j in range(n - 1, -1, -1):
+        v = np.zeros(m)
+        v[j] = 1.0
+        v[j + 1:] = F[j + 1:, j]
+        Q = Q - tau[j] * np.outer(v, v @ Q)
+    return Q
 
 
 def r_chol(A: np.ndarray, F: np.ndarray, matmul=None) -> float:
