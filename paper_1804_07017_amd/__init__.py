@@ -61,6 +61,8 @@ _SIGS = {
     "chol_factor": (_I, [_I, _P, _I, _P]),
     "chol_factor_ex": (_I, [_I, _P, _I, ctypes.POINTER(Schedule), _P, _P]),
     "chol_solve": (_I, [_I, _I, _P, _I, _P, _I, _P]),
+    "qr_factor": (_I, [_I, _I, _P, _I, _P, _P]),
+    "qr_factor_ex": (_I, [_I, _I, _P, _I, _P, ctypes.POINTER(Schedule), _P]),
     "lu_plan_panels": (_I, [_I, _I, _I, _I, ctypes.POINTER(_I), _I]),
     "lu_plan_build_panels": (_I, [_I, ctypes.POINTER(_I), _I, _I, ctypes.POINTER(PlanTask), _I]),
     "lu_k_panel": (_I, [_I, _I, _I, _P, _I, _P, _I, _P, _P]),
@@ -190,6 +192,14 @@ def chol_solve(L, B, stream=None, n=None):
     nrhs = 1 if B.dim() == 1 else B.shape[1]
     return load().chol_solve(n, nrhs, _ptr(L), _ld(L), _ptr(B), _ld(B) if B.dim() > 1 else max(1, n),
                              _stream(stream))
+
+
+def qr_factor(A, tau, sched=None, stream=None):
+    """Householder QR of the column-major device matrix A (m x n, m >= n) in place; tau (n,) device."""
+    m, n = A.shape
+    if sched is None:
+        return load().qr_factor(m, n, _ptr(A), _ld(A), _ptr(tau), _stream(stream))
+    return load().qr_factor_ex(m, n, _ptr(A), _ld(A), _ptr(tau), _sched(sched), _stream(stream))
 
 
 def lu_factor_info():

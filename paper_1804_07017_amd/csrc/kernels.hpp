@@ -102,6 +102,25 @@ struct CholPanelArgs {
 template <typename T>
 int launch_chol_panel(const CholPanelArgs<T>& args, int wgs, hipStream_t stream);
 
+// Householder QR panel (qr.hip): the m x w column block at A (its diagonal at
+// A[0]), FP64, w <= 256, m <= 1024 * wgs; persistent multi-work-group launch.
+struct QrPanelArgs {
+    double* A;
+    long long lda;
+    int m, w;
+    double* tau;           // w reflector scalars (device)
+    double* T;             // w x w upper triangular block-reflector factor, ld w (device)
+    double* part;          // 64 + 64 * 256 doubles of partial sums (device)
+    unsigned* sync;        // [counter, error] of this launch's barrier
+    unsigned* sync_next;   // counter the next launch will use (cleared here)
+    long long spin_limit;
+};
+int launch_qr_panel(const QrPanelArgs& args, int wgs, hipStream_t stream);
+// Vw (m x w, ld m) and VT (w x m, ld w): the panel's unit-lower V, explicit
+int launch_qr_prep(const double* A, long long lda, int m, int w, double* Vw, double* VT, hipStream_t stream);
+// Ym = -T^T W (w x nc, ld w)
+int launch_qr_tmul(const double* T, int w, const double* W, int nc, double* Ym, hipStream_t stream);
+
 // ---- solves and refinement (solve.hip) ----
 // x (n x nrhs, ld) <- P x using per-chunk moves from launch_chunk_moves
 template <typename T>
