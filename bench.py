@@ -117,6 +117,53 @@ def cholesky_leg(lu, n, reps):
             "runs": reps}
 
 
+def qr_leg(lu, n, reps):
+    """FP64 Householder QR with look-ahead (qr_factor, default schedule) of a
+    uniform[-1,1) n x n matrix: median over reps timed factorizations after one
+    warm-up, HIP events on the factorization's stream; the pristine matrix is
+    restored before each run outside the timed region.  GFLOP/s counts the
+    geqrf flops 2mn^2 - 2n^3/3 = 4n^3/3 at m = n."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(11)
+    A0 = lu.colmajor(n)
+    A0.uniform_(-1.0, 1.0, generator=g)
+    A = lu.colmajor(n)
+    tau = torch.zeros(n, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()             # the input is built on the default stream
+    ts = []
+    for r in range(reps + 1):
+        with torch.cuda.stream(stream):
+            A.copy_(A0)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            rc = lu.qr_factor(A, tau, stream=stream)
+            e1.record(stream)
+        stream.synchronize()
+        if rc != 0:
+            raise RuntimeError("qr_factor returned %d" % rc)
+        st, _ = lu.lu_factor_info()
+        if r:
+            ts.append(e0.elapsed_time(e1))
+        print("bench: qr run %d %.1f ms status %d" % (r, e0.elapsed_time(e1), st), file=sys.stderr, flush=True)
+        if st != 0:
+            raise RuntimeError("qr: status %d" % st)
+    t = statistics.median(ts)
+    gf = 4.0 * n ** 3 / 3.0 / (t * 1e-3) / 1e9
+    # |R[0,0]| is the 2-norm of column 0 of A; a cheap sanity check of the run
+    r00 = abs(float(A[0, 0]))
+    c0 = float(torch.linalg.vector_norm(A0[:, 0]))
+    if abs(r00 - c0) > 1e-10 * c0:
+        raise RuntimeError("qr: |R[0,0]| = %r, column norm %r" % (r00, c0))
+    del A0, A, tau
+    torch.cuda.empty_cache()
+    return {"workload": "FP64 Householder QR with look-ahead of a uniform[-1,1) %d x %d matrix" % (n, n),
+            "schedule": {"b": 128, "depth": 2}, "t_factor_ms": round(t, 3), "gflops": round(gf, 1),
+            "flops": "4n^3/3", "pct_fp64_peak": round(100 * gf / 1e3 / FP64_PEAK_TFLOPS, 2), "runs": reps}
+
+
 def cpu_baseline(budget_s=20.0):
     """Time the CPU oracle on a bounded sample of the same workload: one
     factorization of a smaller uniform[-1,1) matrix, sized by cubic
@@ -151,6 +198,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ir", action="store_true")
     ap.add_argument("--no-chol", action="store_true", help="skip the Cholesky measurement")
+    ap.add_argument("--no-qr", action="store_true", help="skip the QR measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the hot path is built and measured on a single MI355X); "
@@ -292,6 +340,8 @@ def main():
                            "avg_launch_gflop": round(gemm_flops / gemm_launches / 1e9, 3)}
     if not args.no_chol:
         out["cholesky"] = cholesky_leg(lu, n, args.steps)
+    if not args.no_qr:
+        out["qr"] = qr_leg(lu, n, args.steps)
     if not args.no_cpu_baseline:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

@@ -37,11 +37,15 @@
 extern "C" {
 #endif
 
-/* Default schedule: b = 128, look-ahead depth 2, 32 panel CUs. */
+/* Default schedule: b = 128, look-ahead depth 2.  The panel kernel runs
+ * ceil(m_k / 1024) work-groups for a panel of m_k rows, so the summation
+ * order inside a panel, and with it the result, is the same for every
+ * schedule at a given b. */
 int qr_factor(int m, int n, double* A, int lda, double* tau, hipStream_t stream);
 
-/* sched: b, depth, panel_cus as in lu_schedule_t (0 / negative = default);
- * taper ignored. */
+/* sched: b and depth as in lu_schedule_t (0 / negative = default);
+ * panel_cus is range-checked only (the panel's group count follows from its
+ * height), taper is ignored. */
 int qr_factor_ex(int m, int n, double* A, int lda, double* tau, const lu_schedule_t* sched, hipStream_t stream);
 
 #ifdef __cplusplus

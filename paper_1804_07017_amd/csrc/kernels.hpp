@@ -110,11 +110,13 @@ struct QrPanelArgs {
     int m, w;
     double* tau;           // w reflector scalars (device)
     double* T;             // w x w upper triangular block-reflector factor, ld w (device)
-    double* part;          // 64 + 64 * 256 doubles of partial sums (device)
+    double* part;          // kQrPartWords doubles of partial sums (device)
     unsigned* sync;        // [counter, error] of this launch's barrier
     unsigned* sync_next;   // counter the next launch will use (cleared here)
     long long spin_limit;
 };
+// workspace of the QR panel: per-group partial sums and the block-phase W
+constexpr int kQrPartWords = 128 + 64 * 16 + 64 * 16 * 256 + 16 * 256;
 int launch_qr_panel(const QrPanelArgs& args, int wgs, hipStream_t stream);
 // Vw (m x w, ld m) and VT (w x m, ld w): the panel's unit-lower V, explicit
 int launch_qr_prep(const double* A, long long lda, int m, int w, double* Vw, double* VT, hipStream_t stream);

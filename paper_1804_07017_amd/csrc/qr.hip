@@ -6,18 +6,33 @@
 // triangular) is applied to the trailing matrix, C <- Q_k^T C =
 // C - V (T^T (V^T C)); the look-ahead of Sec. 4 applies unchanged.
 //
-// Panel kernel: one persistent launch of P work-groups (256 threads each),
-// thread t of group g owning panel rows g*256 + t + s*256*P (s < 4).  Per
-// column j, with two device-wide barriers:
-//   1. each group's partial sum of squares below the diagonal -> barrier;
+// Panel kernel: one persistent launch of P = ceil(m / 1024) work-groups (256
+// threads each), group g owning the 1024-row block starting at g*1024 and
+// thread t its rows g*1024 + t + s*256 (s < 4).  The panel is processed in
+// inner blocks of 16 columns that each thread holds in registers for its rows.
+// Per column J of an inner block, with two device-wide barriers:
+//   1. each group's partial sum of squares below the diagonal (the owner of
+//      row J also publishes the diagonal entry) -> barrier;
 //   2. every group forms the same reflector (beta, tau, 1/(alpha - beta)) from
-//      the partials summed in group order, scales its rows of v;
-//   3. each group's partial dot products v^T A[:, c] for every other panel
-//      column c (rows >= j) -> barrier;
+//      the partials summed in group order and scales its rows of v;
+//   3. each group's partial dot products of v with the other columns of the
+//      inner block (rows >= J) -> barrier;
 //   4. every group sums them in group order, applies the reflector to its rows
-//      of the columns right of j; group 0 stores beta, tau_j and column j of T
-//      (T[0:j, j] = -tau_j T[0:j, 0:j] (V[:, 0:j]^T v_j), T[j, j] = tau_j).
-// Every element sees a fixed operation order whatever P.
+//      of the inner block's columns right of J and extends the inner block's
+//      T (T_b[0:j, j] = -tau_J T_b[0:j, 0:j] (V_b[:, 0:j]^T v_J), T_b[j, j] = tau_J).
+// After an inner block (V_b, T_b), with two more barriers: each group's partial
+// W = V_b^T A[:, c] over its rows for every panel column c outside the block
+// -> barrier; the P partials summed in group order, spread over all groups ->
+// barrier; then every group applies A[:, c] -= V_b (T_b^T W[:, c]) to its rows
+// of the columns right of the block, and the columns left of it (their
+// V^T V_b) give T's block above T_b: T[0:cb, b] = -T[0:cb, 0:cb] (V^T V_b) T_b.
+// The per-column steps touch no memory; the panel is read and written once per
+// inner block.  P and the rows of each group follow from m alone, and every
+// sum runs in a fixed order (rows s, lanes by butterfly, waves, then groups),
+// so the factorization of a given panel is bitwise the same whatever the
+// schedule.
+#include <utility>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -26,8 +41,21 @@ namespace lu {
 namespace {
 
 constexpr int kQrThreads = 256;
-constexpr int kQrRows = 4;          // panel rows per thread (the launch has >= m / 1024 groups)
+constexpr int kQrRows = 4;          // panel rows per thread
+constexpr int kQrGroupRows = kQrThreads * kQrRows;
 constexpr int kQrMaxW = 256;
+constexpr int kQrNB = 16;           // columns of an inner block (held in registers)
+constexpr int kQrWaves = kQrThreads / kWave;
+constexpr int kQrWc = 4;                         // columns per chunk of the block phase
+constexpr int kQrWv = kQrWc * kQrNB;             // values per lane per chunk
+constexpr int kQrRound = 512 / kQrWv;            // chunks per LDS round
+// partial-sum workspace (doubles)
+constexpr int kPartSs = 0;                                   // [64] sums of squares
+constexpr int kPartAlpha = 64;                               // the diagonal entry of column J
+constexpr int kPartDot = 128;                                // [64][16] in-block dot products
+constexpr int kPartW = kPartDot + 64 * kQrNB;                // [64][16 * w] partial W
+constexpr int kPartWs = kPartW + 64 * kQrNB * kQrMaxW;       // [16 * w] summed W
+static_assert(kPartWs + kQrNB * kQrMaxW == kQrPartWords, "QR workspace layout");
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -35,129 +63,312 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Sum over the 64 lanes of a[0..N-1] (N a power of two <= 64) by a butterfly
+// that halves the vector at each exchange: on return the total of element
+// lane / (64 / N) is in a[0].  The order of the additions is fixed.
+template <int N>
+__device__ __forceinline__ double wave_reduce_scatter(double (&a)[N], int lane) {
+    int mask = 32;
+#pragma unroll
+    for (int half = N / 2; half >= 1; half >>= 1, mask >>= 1) {
+        const bool up = (lane & mask) != 0;
+#pragma unroll
+        for (int k = 0; k < half; ++k) {
+            const double lo = a[k], hi = a[k + half];
+            const double send = up ? lo : hi;
+            const double keep = up ? hi : lo;
+            a[k] = keep + __shfl_xor(send, mask, kWave);
+        }
+    }
+#pragma unroll
+    for (; mask >= 1; mask >>= 1) a[0] = a[0] + __shfl_xor(a[0], mask, kWave);
+    return a[0];
+}
+
+struct QrShared {
+    double red[kQrWaves][kQrRound][kQrWv];  // block phase: wave totals of a round of chunks
+    double rw[kQrWaves][kQrNB];             // column step: wave totals
+    double dsum[kQrNB];                     // column step: summed dot products
+    double Tb[kQrNB][kQrNB];                // T of the inner block (upper)
+    double Ys[kQrNB][kQrMaxW];              // T_b^T W of the columns right of the block
+    double Us[kQrMaxW][kQrNB];              // (V^T V_b) T_b of the columns left of it
+    double sc[4];                           // tau, scal, beta
+};
+
+// Where a thread is: its group, lanes and first row.
+struct QrPos {
+    int tid, lane, wave, g, P, row0;
+};
+
+// Column cb + JJ of the inner block held in X (steps 1-4 of the header); false
+// when a barrier timed out.
+template <int JJ>
+__device__ __forceinline__ bool qr_column(double (&X)[kQrRows][kQrNB], QrShared& sh, const QrPanelArgs& a,
+                                          const QrPos& p, int cb, int nbw, unsigned& epoch) {
+    if (JJ >= nbw) return true;
+    const int tid = p.tid, lane = p.lane, wave = p.wave, g = p.g, P = p.P, row0 = p.row0;
+    const int m = a.m;
+    double* part = a.part;
+    const int J = cb + JJ;
+    // 1. partial sum of squares below the diagonal; the owner of row J
+    //    publishes the diagonal entry
+    double ss = 0.0;
+#pragma unroll
+    for (int s = 0; s < kQrRows; ++s) {
+        const int i = row0 + s * kQrThreads;
+        if (i > J && i < m) ss = ss + X[s][JJ] * X[s][JJ];
+        if (i == J) part[kPartAlpha] = X[s][JJ];
+    }
+    ss = wave_sum(ss);
+    if (lane == 0) sh.rw[wave][0] = ss;
+    __syncthreads();
+    if (tid == 0) part[kPartSs + g] = (sh.rw[0][0] + sh.rw[1][0]) + (sh.rw[2][0] + sh.rw[3][0]);
+    if (grid_barrier(a.sync, a.sync + 1, ++epoch, a.spin_limit)) return false;
+    // 2. the reflector, identical in every group
+    if (tid == 0) {
+        double sig = 0.0;
+        for (int q = 0; q < P; ++q) sig = sig + part[kPartSs + q];
+        const double alpha = part[kPartAlpha];
+        double tau = 0.0, scal = 1.0, beta = alpha;
+        if (sig != 0.0) {
+            const double nrm = sqrt(alpha * alpha + sig);
+            beta = alpha >= 0.0 ? -nrm : nrm;
+            tau = (beta - alpha) / beta;
+            scal = 1.0 / (alpha - beta);
+        }
+        sh.sc[0] = tau; sh.sc[1] = scal; sh.sc[2] = beta;
+    }
+    __syncthreads();
+    const double tau = sh.sc[0], scal = sh.sc[1];
+    double v[kQrRows];
+#pragma unroll
+    for (int s = 0; s < kQrRows; ++s) {
+        const int i = row0 + s * kQrThreads;
+        v[s] = 0.0;
+        if (i == J) {
+            v[s] = 1.0;
+            X[s][JJ] = sh.sc[2];
+        } else if (i > J && i < m) {
+            double x = X[s][JJ];
+            if (tau != 0.0) {
+                x = x * scal;
+                X[s][JJ] = x;
+            }
+            v[s] = x;
+        }
+    }
+    // 3. partial dot products of v with the block's other columns
+    if (tau != 0.0) {
+        double d[kQrNB];
+#pragma unroll
+        for (int c = 0; c < kQrNB; ++c) {
+            double acc = 0.0;
+            if (c != JJ) {
+#pragma unroll
+                for (int s = 0; s < kQrRows; ++s) {
+                    const int i = row0 + s * kQrThreads;
+                    if (i >= J && i < m) acc = acc + v[s] * X[s][c];
+                }
+            }
+            d[c] = acc;
+        }
+        const double dl = wave_reduce_scatter<kQrNB>(d, lane);
+        if ((lane & (kWave / kQrNB - 1)) == 0) sh.rw[wave][lane / (kWave / kQrNB)] = dl;
+    }
+    __syncthreads();
+    if (tau != 0.0 && tid < nbw && tid != JJ)
+        part[kPartDot + g * kQrNB + tid] = (sh.rw[0][tid] + sh.rw[1][tid]) + (sh.rw[2][tid] + sh.rw[3][tid]);
+    if (grid_barrier(a.sync, a.sync + 1, ++epoch, a.spin_limit)) return false;
+    // 4. sums in group order; the block's columns right of J; T_b column JJ
+    if (tid < kQrNB) {
+        double sum = 0.0;
+        if (tau != 0.0 && tid < nbw && tid != JJ)
+            for (int q = 0; q < P; ++q) sum = sum + part[kPartDot + q * kQrNB + tid];
+        sh.dsum[tid] = sum;
+    }
+    __syncthreads();
+    if (tau != 0.0) {
+#pragma unroll
+        for (int c = JJ + 1; c < kQrNB; ++c) {
+            const double t = -tau * sh.dsum[c];
+#pragma unroll
+            for (int s = 0; s < kQrRows; ++s) {
+                const int i = row0 + s * kQrThreads;
+                if (i >= J && i < m) X[s][c] = X[s][c] + v[s] * t;
+            }
+        }
+    }
+    if (tid < JJ) {
+        double acc = 0.0;
+        if (tau != 0.0)
+            for (int l = tid; l < JJ; ++l) acc = acc + sh.Tb[tid][l] * sh.dsum[l];
+        sh.Tb[tid][JJ] = -tau * acc;
+    }
+    if (tid == 0) {
+        sh.Tb[JJ][JJ] = tau;
+        if (g == 0) a.tau[J] = tau;
+    }
+    __syncthreads();             // rw, sc, dsum and Tb are rewritten by the next column
+    return true;
+}
+
+template <int... Js>
+__device__ __forceinline__ bool qr_columns(std::integer_sequence<int, Js...>, double (&X)[kQrRows][kQrNB],
+                                           QrShared& sh, const QrPanelArgs& a, const QrPos& p, int cb, int nbw,
+                                           unsigned& epoch) {
+    return (qr_column<Js>(X, sh, a, p, cb, nbw, epoch) && ...);
+}
+
 __global__ __launch_bounds__(kQrThreads) void qr_panel_kernel(QrPanelArgs a) {
-    __shared__ double red[kQrThreads / kWave][kQrMaxW];
-    __shared__ double wv[kQrMaxW];
-    __shared__ double sc[4];                 // tau, scal, beta
+    __shared__ QrShared sh;
+    auto& red = sh.red;
+    auto& Tb = sh.Tb;
+    auto& Ys = sh.Ys;
+    auto& Us = sh.Us;
     const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
     const int g = blockIdx.x, P = gridDim.x;
     const int m = a.m, w = a.w;
     const long long lda = a.lda;
     double* __restrict__ A = a.A;
-    const int stride = kQrThreads * P;
-    const int row0 = g * kQrThreads + tid;
+    const int row0 = g * kQrGroupRows + tid;
     unsigned epoch = 0;
     if (g == 0 && tid == 0 && a.sync_next) a.sync_next[0] = 0u;
-    double* part1 = a.part;                  // [P]
-    double* part3 = a.part + 64;             // [P][w]
+    double* part = a.part;
+    const int ww = kQrNB * w;                      // entries of one group's partial W
 
-    for (int j = 0; j < w; ++j) {
-        double* colj = A + (long long)j * lda;
-        // 1. partial sum of squares of column j below the diagonal
-        double ss = 0.0;
+    for (int cb = 0; cb < w; cb += kQrNB) {
+        const int nbw = min(kQrNB, w - cb);
+        double X[kQrRows][kQrNB];
 #pragma unroll
         for (int s = 0; s < kQrRows; ++s) {
-            const int i = row0 + s * stride;
-            if (i > j && i < m) {
-                const double x = colj[i];
-                ss = ss + x * x;
-            }
+            const long long r = min(row0 + s * kQrThreads, m - 1);
+#pragma unroll
+            for (int c = 0; c < kQrNB; ++c) X[s][c] = A[r + (long long)min(cb + c, w - 1) * lda];
         }
-        ss = wave_sum(ss);
-        if (lane == 0) red[wave][0] = ss;
-        __syncthreads();
-        if (tid == 0) part1[g] = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
-        if (grid_barrier(a.sync, a.sync + 1, ++epoch, a.spin_limit)) return;
-        // 2. the reflector, identical in every group
-        if (tid == 0) {
-            double sig = 0.0;
-            for (int q = 0; q < P; ++q) sig = sig + part1[q];
-            const double alpha = colj[j];
-            double tau = 0.0, scal = 1.0, beta = alpha;
-            if (sig != 0.0) {
-                const double nrm = sqrt(alpha * alpha + sig);
-                beta = alpha >= 0.0 ? -nrm : nrm;
-                tau = (beta - alpha) / beta;
-                scal = 1.0 / (alpha - beta);
-            }
-            sc[0] = tau; sc[1] = scal; sc[2] = beta;
+        Tb[tid / kQrNB][tid % kQrNB] = 0.0;        // 256 threads = 16 x 16 entries
+
+        {
+            const QrPos pos{tid, lane, wave, g, P, row0};
+            if (!qr_columns(std::make_integer_sequence<int, kQrNB>{}, X, sh, a, pos, cb, nbw, epoch)) return;
         }
-        __syncthreads();
-        const double tau = sc[0], scal = sc[1];
-        double v[kQrRows];
+
+        // the inner block's R and V back to memory; then X <- V_b (unit lower, 0 outside)
 #pragma unroll
         for (int s = 0; s < kQrRows; ++s) {
-            const int i = row0 + s * stride;
-            v[s] = 0.0;
-            if (i == j) v[s] = 1.0;
-            else if (i > j && i < m) {
-                double x = colj[i];
-                if (tau != 0.0) {
-                    x = x * scal;
-                    colj[i] = x;
-                }
-                v[s] = x;
-            }
-        }
-        // 3. partial dot products v^T A[:, c] (rows >= j) for every panel column c != j
-        if (tau != 0.0) {
-            for (int c = 0; c < w; ++c) {
-                if (c == j) continue;
-                const double* colc = A + (long long)c * lda;
-                double acc = 0.0;
+            const int i = row0 + s * kQrThreads;
 #pragma unroll
-                for (int s = 0; s < kQrRows; ++s) {
-                    const int i = row0 + s * stride;
-                    if (i >= j && i < m) acc = acc + v[s] * colc[i];
-                }
-                acc = wave_sum(acc);
-                if (lane == 0) red[wave][c] = acc;
-            }
-        }
-        __syncthreads();
-        if (tau != 0.0) {
-            for (int c = tid; c < w; c += kQrThreads)
-                if (c != j) part3[(size_t)g * kQrMaxW + c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
-        }
-        if (grid_barrier(a.sync, a.sync + 1, ++epoch, a.spin_limit)) return;
-        // 4. sums in group order; the reflector applied to the columns right of j
-        if (tau != 0.0) {
-            for (int c = tid; c < w; c += kQrThreads) {
-                double sum = 0.0;
-                if (c != j)
-                    for (int q = 0; q < P; ++q) sum = sum + part3[(size_t)q * kQrMaxW + c];
-                wv[c] = sum;
-            }
-        }
-        __syncthreads();
-        if (tau != 0.0) {
-            for (int c = j + 1; c < w; ++c) {
-                double* colc = A + (long long)c * lda;
-                const double t = -tau * wv[c];
-#pragma unroll
-                for (int s = 0; s < kQrRows; ++s) {
-                    const int i = row0 + s * stride;
-                    if (i >= j && i < m) colc[i] = colc[i] + v[s] * t;
-                }
+            for (int c = 0; c < kQrNB; ++c) {
+                if (i < m && c < nbw) A[i + (long long)(cb + c) * lda] = X[s][c];
+                const int d = cb + c;
+                X[s][c] = (c >= nbw || i >= m || i < d) ? 0.0 : (i == d ? 1.0 : X[s][c]);
             }
         }
         if (g == 0) {
-            // T[0:j, j] = -tau T[0:j, 0:j] s(0:j), s(l) = V[:, l]^T v_j
-            double* T = a.T;
-            for (int r = tid; r < j; r += kQrThreads) {
-                double acc = 0.0;
-                if (tau != 0.0)
-                    for (int l = r; l < j; ++l) acc = acc + T[r + (long long)l * w] * wv[l];
-                T[r + (long long)j * w] = -tau * acc;
-            }
-            if (tid == 0) {
-                T[j + (long long)j * w] = tau;
-                a.tau[j] = tau;
-                colj[j] = sc[2];
-            }
-            __threadfence_block();
+            const int r = tid / kQrNB, c = tid % kQrNB;
+            if (r <= c && c < nbw) a.T[(cb + r) + (long long)(cb + c) * w] = Tb[r][c];
         }
-        __syncthreads();     // wv, sc and red are rewritten by the next column
+        if (w == nbw) break;                 // a single inner block: nothing outside it
+
+        // 5. partial W[:, c] = V_b^T A[:, c] over the group's rows, for the panel
+        //    columns left (c < cb) and right (c >= cb + 16) of the block, in
+        //    chunks of kQrWc columns (value cc * 16 + l of a chunk ends in lanes
+        //    (64 / kQrWv) * (cc * 16 + l) after the reduce-scatter)
+        double* Wp = part + kPartW + (size_t)g * ww;
+        const int nleft = cb / kQrWc, nright = (w - (cb + kQrNB) + kQrWc - 1) / kQrWc;
+        const int nch = nleft + (nright > 0 ? nright : 0);
+        for (int r0 = 0; r0 < nch; r0 += kQrRound) {
+            const int rn = min(kQrRound, nch - r0);
+            for (int k = 0; k < rn; ++k) {
+                const int ch = r0 + k;
+                const int c0 = ch < nleft ? kQrWc * ch : cb + kQrNB + kQrWc * (ch - nleft);
+                double x[kQrRows][kQrWc];
+#pragma unroll
+                for (int s = 0; s < kQrRows; ++s) {
+                    const long long r = min(row0 + s * kQrThreads, m - 1);
+#pragma unroll
+                    for (int cc = 0; cc < kQrWc; ++cc) x[s][cc] = A[r + (long long)min(c0 + cc, w - 1) * lda];
+                }
+                double acc[kQrWv];
+#pragma unroll
+                for (int cc = 0; cc < kQrWc; ++cc)
+#pragma unroll
+                    for (int l = 0; l < kQrNB; ++l) {
+                        double t = 0.0;
+#pragma unroll
+                        for (int s = 0; s < kQrRows; ++s) t = t + X[s][l] * x[s][cc];
+                        acc[cc * kQrNB + l] = t;
+                    }
+                const double tot = wave_reduce_scatter<kQrWv>(acc, lane);
+                if ((lane & (kWave / kQrWv - 1)) == 0) red[wave][k][lane / (kWave / kQrWv)] = tot;
+            }
+            __syncthreads();
+            for (int e = tid; e < rn * kQrWv; e += kQrThreads) {
+                const int k = e / kQrWv, ev = e % kQrWv;
+                const int ch = r0 + k;
+                const int c = (ch < nleft ? kQrWc * ch : cb + kQrNB + kQrWc * (ch - nleft)) + ev / kQrNB;
+                if (c < w)
+                    Wp[(ev % kQrNB) + kQrNB * c] = (red[0][k][ev] + red[1][k][ev]) + (red[2][k][ev] + red[3][k][ev]);
+            }
+            __syncthreads();
+        }
+        if (grid_barrier(a.sync, a.sync + 1, ++epoch, a.spin_limit)) return;
+        // 6. the P partials summed in group order, entries spread over all groups
+        for (int e = g * kQrThreads + tid; e < ww; e += kQrThreads * P) {
+            const int c = e / kQrNB;
+            if (c >= cb && c < cb + kQrNB) continue;
+            double sum = 0.0;
+            for (int q = 0; q < P; ++q) sum = sum + part[kPartW + (size_t)q * ww + e];
+            part[kPartWs + e] = sum;
+        }
+        if (grid_barrier(a.sync, a.sync + 1, ++epoch, a.spin_limit)) return;
+        // 7. Y = T_b^T W for the columns right of the block; their update
+        const double* Ws = part + kPartWs;
+        const int c1 = cb + kQrNB, nr = w - c1;
+        for (int e = tid; e < kQrNB * (nr > 0 ? nr : 0); e += kQrThreads) {
+            const int l = e % kQrNB, c = e / kQrNB;
+            double acc = 0.0;
+            for (int p = 0; p <= l; ++p) acc = acc + Tb[p][l] * Ws[p + kQrNB * (c1 + c)];
+            Ys[l][c] = acc;
+        }
+        // (V^T V_b) T_b for the columns left of it
+        for (int e = tid; e < cb * kQrNB; e += kQrThreads) {
+            const int q = e % kQrNB, c = e / kQrNB;
+            double acc = 0.0;
+            for (int l = 0; l <= q; ++l) acc = acc + Ws[l + kQrNB * c] * Tb[l][q];
+            Us[c][q] = acc;
+        }
+        __syncthreads();
+        for (int c00 = c1; c00 < w; c00 += 4) {
+            double x[kQrRows][4];
+#pragma unroll
+            for (int s = 0; s < kQrRows; ++s) {
+                const long long r = min(row0 + s * kQrThreads, m - 1);
+#pragma unroll
+                for (int cc = 0; cc < 4; ++cc) x[s][cc] = A[r + (long long)min(c00 + cc, w - 1) * lda];
+            }
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) {
+                const int c = c00 + cc;
+                if (c < w) {
+#pragma unroll
+                    for (int s = 0; s < kQrRows; ++s) {
+                        const int i = row0 + s * kQrThreads;
+                        double t = 0.0;
+#pragma unroll
+                        for (int l = 0; l < kQrNB; ++l) t = t + X[s][l] * Ys[l][c - c1];
+                        if (i >= cb && i < m) A[i + (long long)c * lda] = x[s][cc] - t;
+                    }
+                }
+            }
+        }
+        // T[0:cb, block] = -T[0:cb, 0:cb] U, rows of T spread over the groups
+        for (int e = g * kQrThreads + tid; e < cb * nbw; e += kQrThreads * P) {
+            const int r = e % cb, q = e / cb;
+            double acc = 0.0;
+            for (int c = r; c < cb; ++c) acc = acc + a.T[r + (long long)c * w] * Us[c][q];
+            a.T[r + (long long)(cb + q) * w] = -acc;
+        }
+        __syncthreads();                     // Tb, Ys and Us are rewritten by the next block
     }
 }
 
@@ -199,7 +410,7 @@ inline int grid_for(long long work) {
 
 int launch_qr_panel(const QrPanelArgs& args, int wgs, hipStream_t stream) {
     if (args.w < 1 || args.w > kQrMaxW || args.m < args.w || wgs < 1 || wgs > 64) return -1;
-    if ((long long)wgs * kQrThreads * kQrRows < args.m) return -1;
+    if (wgs != (args.m + kQrThreads * kQrRows - 1) / (kQrThreads * kQrRows)) return -1;
     hipLaunchKernelGGL(qr_panel_kernel, dim3(wgs), dim3(kQrThreads), 0, stream, args);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }

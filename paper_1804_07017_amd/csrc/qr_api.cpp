@@ -20,11 +20,10 @@ namespace lu {
 namespace {
 
 constexpr int kQrSlots = 4;
-constexpr int kQrPartWords = 64 + 64 * 256;
 
 bool qr_valid_b(int b) { return b == 32 || b == 64 || b == 128 || b == 256; }
 
-int qr_execute(DeviceState* s, int m, int n, double* A, long long lda, double* tau, int b, int depth, int panel_cus,
+int qr_execute(DeviceState* s, int m, int n, double* A, long long lda, double* tau, int b, int depth,
                hipStream_t stream) {
     std::vector<int> starts;
     for (int c = 0; c < n; c += b) starts.push_back(c);
@@ -85,12 +84,10 @@ int qr_execute(DeviceState* s, int m, int n, double* A, long long lda, double* t
             pa.sync_next = s->sync + 2 * (1 - s->sync_slot);
             s->sync_slot = 1 - s->sync_slot;
             pa.spin_limit = s->spin_limit;
-            // one group per 1024 rows (4 per thread), at least the panel CU share,
-            // at most 64 and the CU count (every group resident at once)
-            int wgs = std::max((mk + 1023) / 1024, std::max(1, panel_cus));
-            wgs = std::min(wgs, std::min(64, s->num_cus));
-            wgs = std::min(wgs, std::max(1, (mk + 255) / 256));
-            if ((long long)wgs * 1024 < mk) return LU_ERR_UNSUPPORTED;
+            // one group per 1024 rows (4 per thread), fixed by the panel height so
+            // that the reduction order does not depend on the schedule
+            const int wgs = (mk + 1023) / 1024;
+            if (wgs > 64 || wgs > s->num_cus) return LU_ERR_UNSUPPORTED;
             if (launch_qr_panel(pa, wgs, st)) return LU_ERR_HIP;
             if (launch_qr_prep(pa.A, lda, mk, wk, Vk, VTk, st)) return LU_ERR_HIP;
         } else if (t.kind == kTaskUpdate) {
@@ -128,13 +125,12 @@ int qr_factor_impl(int m, int n, double* A, int lda, double* tau, const lu_sched
     if (!A && n > 0) return -3;
     if (lda < std::max(1, m)) return -4;
     if (!tau && n > 0) return -5;
-    int b = 128, depth = 2, panel_cus = 32;
+    int b = 128, depth = 2;
     if (sched) {
         if (sched->b > 0 && !qr_valid_b(sched->b)) return -6;
         if (sched->depth > 2 || sched->panel_cus > 256) return -6;
         if (sched->b > 0) b = sched->b;
         if (sched->depth >= 0 && (sched->b > 0 || sched->depth > 0 || sched->panel_cus > 0)) depth = sched->depth;
-        if (sched->panel_cus > 0) panel_cus = sched->panel_cus;
     }
     if (n == 0) return 0;
     int err;
@@ -146,7 +142,7 @@ int qr_factor_impl(int m, int n, double* A, int lda, double* tau, const lu_sched
     if (launch_fill_zero(s->info, sizeof(int), stream)) return LU_ERR_HIP;
     s->last_stream = stream;
     s->last_info = s->info;
-    return qr_execute(s, m, n, A, lda, tau, b, depth, panel_cus, stream);
+    return qr_execute(s, m, n, A, lda, tau, b, depth, stream);
 }
 
 }  // namespace lu

@@ -36,7 +36,7 @@ def test_qr_matches_oracle(gpu, m, n, b, depth, cus, lda):
 
 
 def test_qr_schedule_invariance_bitwise(gpu):
-    A = synth.uniform(1500, seed=31)
+    A = synth.uniform(2600, seed=31)
     ref = None
     for depth in (0, 1, 2):
         for cus in (8, 16, 32):
