@@ -110,6 +110,10 @@ DeviceState* device_state(int* err) {
         const int v = std::atoi(e);
         if (v > 0) s->wide_rows = v;
     }
+    if (const char* e = std::getenv("QR_SPLIT_ROWS")) {
+        const int v = std::atoi(e);
+        if (v >= 256 && v % 16 == 0) s->qr_split_rows = v;
+    }
     if (const char* e = std::getenv("LU_DEBUG_BARRIER_SPIN")) {
         long long v = std::atoll(e);
         if (v > 0) s->spin_limit = v;                    // debug knob: tiny bound forces the timeout path
@@ -144,7 +148,7 @@ void release_all() {
         if (s->info) hipFree(s->info);
         Buffer* bufs[] = {&s->cand, &s->moves, &s->linv, &s->lh, &s->uh, &s->rs, &s->cs, &s->solve_moves, &s->flags,
                           &s->partial, &s->ir_r, &s->ir_x32, &s->ir_a32, &s->ir_a64, &s->ir_norms, &s->ir_ipiv,
-                          &s->ir_b, &s->qr_v, &s->qr_vt, &s->qr_t, &s->qr_w, &s->qr_ym, &s->qr_part};
+                          &s->ir_b, &s->qr_v, &s->qr_vt, &s->qr_t, &s->qr_tt, &s->qr_w, &s->qr_ws, &s->qr_ym, &s->qr_part};
         for (Buffer* b : bufs) release(*b);
         delete s;
     }

@@ -56,7 +56,7 @@ __device__ __forceinline__ void tile_of(int tiles_m, int tiles_n, int& tm, int& 
 // same column block.  LOW: only C's lower triangle is updated -- element
 // (i, j) of C when i + diag >= j -- tiles wholly above it are skipped and
 // tiles across it store only their lower part.
-template <typename T, int BK, bool TB, bool LOW>
+template <typename T, int BK, bool TB, bool LOW, bool ZERO = false>
 __device__ __forceinline__ void gemm_tile(int M, int N, int K, const T* __restrict__ A, int lda,
                                           const T* __restrict__ B, int ldb, T* __restrict__ C, int ldc,
                                           int diag) {
@@ -85,10 +85,17 @@ __device__ __forceinline__ void gemm_tile(int M, int N, int K, const T* __restri
     // LOW: tiles wholly below the diagonal store everything
     const bool full = !LOW || m0 + diag >= n0 + kBN - 1;
 
-    // accumulators start from C
+    // accumulators start from C (ZERO: from 0, C is only written)
     V4 acc[4][4];
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
+        if constexpr (ZERO) {
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[rb][cb][r] = T(0);
+            continue;
+        }
         const int row = m0 + wm * 64 + rb * 16 + l16;
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
@@ -210,6 +217,22 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_nn_sub(int M, int N, int K, 
                                                             int lda, const T* __restrict__ B, int ldb,
                                                             T* __restrict__ C, int ldc) {
     gemm_tile<T, BK, false, false>(M, N, K, A, lda, B, ldb, C, ldc, 0);
+}
+
+// Split-K form for products with a long k range and few output tiles (the
+// V^T C product of a Householder block update): the work-groups of slice
+// z = blockIdx.y take k in [z*ks, min(K, (z+1)*ks)) and store
+// C_z = -A[:, slice] B[slice, :] at C + z*cstride.  Summing the slices in z
+// order gives a result that depends on ks only, not on the launch.
+template <typename T, int BK>
+__global__ __launch_bounds__(kThreads, 2) void gemm_nn_split(int M, int N, int K, int ks,
+                                                              const T* __restrict__ A, int lda,
+                                                              const T* __restrict__ B, int ldb,
+                                                              T* __restrict__ C, int ldc, long long cstride) {
+    const int z = blockIdx.y;
+    const int k0 = z * ks;
+    gemm_tile<T, BK, false, false, true>(M, N, min(ks, K - k0), A + (long long)k0 * lda, lda, B + k0, ldb,
+                                         C + z * cstride, ldc, 0);
 }
 
 // C -= A B^T on the lower triangle of C (the symmetric rank-k update of a
@@ -392,6 +415,19 @@ int launch_gemm(int M, int N, int K, const T* A, int lda, const T* B, int ldb, T
 }
 
 template <typename T>
+int launch_gemm_split(int M, int N, int K, int ks, const T* A, int lda, const T* B, int ldb, T* C, int ldc,
+                      long long cstride, hipStream_t stream) {
+    if (M <= 0 || N <= 0 || K <= 0) return 0;
+    if (ks <= 0) return -1;
+    const int tiles = ((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
+    const int splits = (K + ks - 1) / ks;
+    if (splits > 65535) return -1;
+    hipLaunchKernelGGL((gemm_nn_split<T, 16>), dim3(tiles, splits), dim3(kThreads), 0, stream, M, N, K, ks, A,
+                       lda, B, ldb, C, ldc, cstride);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+template <typename T>
 int launch_syrk_lower(int M, int N, int K, const T* A, int lda, const T* B, int ldb, T* C, int ldc, int diag,
                       hipStream_t stream) {
     if (M <= 0 || N <= 0 || K <= 0) return 0;
@@ -415,6 +451,8 @@ int launch_gemm_half(int M, int N, int K, const H* Ah, int lda_h, const H* Bh, i
 template int launch_gemm<double>(int, int, int, const double*, int, const double*, int, double*, int,
                                  hipStream_t);
 template int launch_gemm<float>(int, int, int, const float*, int, const float*, int, float*, int, hipStream_t);
+template int launch_gemm_split<double>(int, int, int, int, const double*, int, const double*, int, double*, int,
+                                       long long, hipStream_t);
 template int launch_syrk_lower<double>(int, int, int, const double*, int, const double*, int, double*, int, int,
                                        hipStream_t);
 template int launch_gemm_half<_Float16>(int, int, int, const _Float16*, int, const _Float16*, int,

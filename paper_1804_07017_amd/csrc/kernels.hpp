@@ -75,6 +75,10 @@ int launch_cols_half(const float* B, long long ldb, int k, int n, H* Uh, long lo
 
 template <typename T>
 int launch_gemm(int M, int N, int K, const T* A, int lda, const T* B, int ldb, T* C, int ldc, hipStream_t stream);
+// slices z of ks k-values: C + z*cstride = -A[:, slice] B[slice, :] (not accumulated)
+template <typename T>
+int launch_gemm_split(int M, int N, int K, int ks, const T* A, int lda, const T* B, int ldb, T* C, int ldc,
+                      long long cstride, hipStream_t stream);
 template <typename H>
 int launch_gemm_half(int M, int N, int K, const H* Ah, int lda_h, const H* Bh, int ldb_h, const float* rs,
                      const float* cs, float* C, int ldc, hipStream_t stream);
@@ -118,10 +122,12 @@ struct QrPanelArgs {
 // workspace of the QR panel: per-group partial sums and the block-phase W
 constexpr int kQrPartWords = 128 + 64 * 16 + 64 * 16 * 256 + 16 * 256;
 int launch_qr_panel(const QrPanelArgs& args, int wgs, hipStream_t stream);
-// Vw (m x w, ld m) and VT (w x m, ld w): the panel's unit-lower V, explicit
-int launch_qr_prep(const double* A, long long lda, int m, int w, double* Vw, double* VT, hipStream_t stream);
-// Ym = -T^T W (w x nc, ld w)
-int launch_qr_tmul(const double* T, int w, const double* W, int nc, double* Ym, hipStream_t stream);
+// Vw (m x w, ld m) and VT (w x m, ld w): the panel's unit-lower V, explicit;
+// TT = T^T (w x w, ld w)
+int launch_qr_prep(const double* A, long long lda, int m, int w, const double* T, double* Vw, double* VT,
+                   double* TT, hipStream_t stream);
+// W = sum of the S k-slices Wp[s * count ...] in slice order
+int launch_qr_wsum(const double* Wp, int S, long long count, double* W, hipStream_t stream);
 
 // ---- solves and refinement (solve.hip) ----
 // x (n x nrhs, ld) <- P x using per-chunk moves from launch_chunk_moves

@@ -373,9 +373,11 @@ __global__ __launch_bounds__(kQrThreads) void qr_panel_kernel(QrPanelArgs a) {
 }
 
 // V of the panel as two explicit operands for the trailing update: Vw (m x w,
-// column-major, ld m) and its transpose VT (w x m, ld w), unit lower.
+// column-major, ld m) and its transpose VT (w x m, ld w), unit lower; and
+// TT = T^T (w x w, ld w, zero above the diagonal).
 __global__ __launch_bounds__(256) void qr_prep_kernel(const double* __restrict__ A, long long lda, int m, int w,
-                                                      double* __restrict__ Vw, double* __restrict__ VT) {
+                                                      const double* __restrict__ T, double* __restrict__ Vw,
+                                                      double* __restrict__ VT, double* __restrict__ TT) {
     const long long total = (long long)m * w;
     for (long long e = blockIdx.x * 256ll + threadIdx.x; e < total; e += (long long)gridDim.x * 256) {
         const int i = (int)(e % m);
@@ -383,19 +385,17 @@ __global__ __launch_bounds__(256) void qr_prep_kernel(const double* __restrict__
         const double v = i > c ? A[i + (long long)c * lda] : (i == c ? 1.0 : 0.0);
         Vw[i + (long long)c * m] = v;
         VT[c + (long long)i * w] = v;
+        if (i < w) TT[i + (long long)c * w] = i >= c ? T[c + (long long)i * w] : 0.0;
     }
 }
 
-// Ym = -T^T W (w x nc, both column-major with ld w); T upper triangular.
-__global__ __launch_bounds__(256) void qr_tmul_kernel(const double* __restrict__ T, int w, const double* __restrict__ W,
-                                                      int nc, double* __restrict__ Ym) {
-    const long long total = (long long)w * nc;
-    for (long long e = blockIdx.x * 256ll + threadIdx.x; e < total; e += (long long)gridDim.x * 256) {
-        const int r = (int)(e % w);
-        const long long col = e / w;
-        double acc = 0.0;
-        for (int l = 0; l <= r; ++l) acc = acc + T[l + (long long)r * w] * W[l + col * w];
-        Ym[r + col * w] = -acc;
+// W = sum over s < S of the k-slices Wp[s * count + e], in s order.
+__global__ __launch_bounds__(256) void qr_wsum_kernel(const double* __restrict__ Wp, int S, long long count,
+                                                      double* __restrict__ W) {
+    for (long long e = blockIdx.x * 256ll + threadIdx.x; e < count; e += (long long)gridDim.x * 256) {
+        double acc = Wp[e];
+        for (int z = 1; z < S; ++z) acc = acc + Wp[(long long)z * count + e];
+        W[e] = acc;
     }
 }
 
@@ -415,15 +415,17 @@ int launch_qr_panel(const QrPanelArgs& args, int wgs, hipStream_t stream) {
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-int launch_qr_prep(const double* A, long long lda, int m, int w, double* Vw, double* VT, hipStream_t stream) {
-    if (m <= 0 || w <= 0) return 0;
-    hipLaunchKernelGGL(qr_prep_kernel, dim3(grid_for((long long)m * w)), dim3(256), 0, stream, A, lda, m, w, Vw, VT);
+int launch_qr_prep(const double* A, long long lda, int m, int w, const double* T, double* Vw, double* VT,
+                   double* TT, hipStream_t stream) {
+    if (m <= 0 || w <= 0 || m < w) return 0;
+    hipLaunchKernelGGL(qr_prep_kernel, dim3(grid_for((long long)m * w)), dim3(256), 0, stream, A, lda, m, w, T, Vw,
+                       VT, TT);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-int launch_qr_tmul(const double* T, int w, const double* W, int nc, double* Ym, hipStream_t stream) {
-    if (w <= 0 || nc <= 0) return 0;
-    hipLaunchKernelGGL(qr_tmul_kernel, dim3(grid_for((long long)w * nc)), dim3(256), 0, stream, T, w, W, nc, Ym);
+int launch_qr_wsum(const double* Wp, int S, long long count, double* W, hipStream_t stream) {
+    if (S <= 0 || count <= 0) return 0;
+    hipLaunchKernelGGL(qr_wsum_kernel, dim3(grid_for(count)), dim3(256), 0, stream, Wp, S, count, W);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 

@@ -36,12 +36,20 @@ int qr_execute(DeviceState* s, int m, int n, double* A, long long lda, double* t
     if ((rc = ensure(s->qr_v, kQrSlots * vwords * sizeof(double)))) return rc;
     if ((rc = ensure(s->qr_vt, kQrSlots * vwords * sizeof(double)))) return rc;
     if ((rc = ensure(s->qr_t, (size_t)kQrSlots * b * b * sizeof(double)))) return rc;
+    if ((rc = ensure(s->qr_tt, (size_t)kQrSlots * b * b * sizeof(double)))) return rc;
+    // V^T C in k-slices of ks rows (fixed per factorization: the slice sums,
+    // and so the result, do not depend on how the update is split by columns)
+    const int ks = s->qr_split_rows;
+    const int max_slices = (m + ks - 1) / ks;
+    if (max_slices > 1 && (rc = ensure(s->qr_ws, 2 * (size_t)max_slices * b * n * sizeof(double)))) return rc;
     if ((rc = ensure(s->qr_w, 2 * (size_t)b * n * sizeof(double)))) return rc;
     if ((rc = ensure(s->qr_ym, 2 * (size_t)b * n * sizeof(double)))) return rc;
     if ((rc = ensure(s->qr_part, (size_t)kQrPartWords * sizeof(double)))) return rc;
     double* V = reinterpret_cast<double*>(s->qr_v.ptr);
     double* VT = reinterpret_cast<double*>(s->qr_vt.ptr);
     double* Tb = reinterpret_cast<double*>(s->qr_t.ptr);
+    double* TTb = reinterpret_cast<double*>(s->qr_tt.ptr);
+    double* WSb = max_slices > 1 ? reinterpret_cast<double*>(s->qr_ws.ptr) : nullptr;
     double* Wb = reinterpret_cast<double*>(s->qr_w.ptr);
     double* Yb = reinterpret_cast<double*>(s->qr_ym.ptr);
     size_t nrec = 0;
@@ -71,6 +79,7 @@ int qr_execute(DeviceState* s, int m, int n, double* A, long long lda, double* t
         double* Vk = V + slot * vwords;
         double* VTk = VT + slot * vwords;
         double* Tk = Tb + (size_t)slot * b * b;
+        double* TTk = TTb + (size_t)slot * b * b;
         if (t.kind == kTaskPanel) {
             QrPanelArgs pa;
             pa.A = A + kb + (long long)kb * lda;
@@ -89,15 +98,20 @@ int qr_execute(DeviceState* s, int m, int n, double* A, long long lda, double* t
             const int wgs = (mk + 1023) / 1024;
             if (wgs > 64 || wgs > s->num_cus) return LU_ERR_UNSUPPORTED;
             if (launch_qr_panel(pa, wgs, st)) return LU_ERR_HIP;
-            if (launch_qr_prep(pa.A, lda, mk, wk, Vk, VTk, st)) return LU_ERR_HIP;
+            if (launch_qr_prep(pa.A, lda, mk, wk, Tk, Vk, VTk, TTk, st)) return LU_ERR_HIP;
         } else if (t.kind == kTaskUpdate) {
             const int c0 = t.col_begin, nc = t.col_end - t.col_begin;
             double* W = Wb + (size_t)(t.stream == 1 ? 1 : 0) * b * n;
             double* Ym = Yb + (size_t)(t.stream == 1 ? 1 : 0) * b * n;
             double* C = A + kb + (long long)c0 * lda;
-            if (launch_fill_zero(W, (size_t)wk * nc * sizeof(double), st)) return LU_ERR_HIP;
-            if (launch_gemm<double>(wk, nc, mk, VTk, wk, C, (int)lda, W, wk, st)) return LU_ERR_HIP;   // W = -V^T C
-            if (launch_qr_tmul(Tk, wk, W, nc, Ym, st)) return LU_ERR_HIP;                           // Ym = -T^T W
+            const int slices = (mk + ks - 1) / ks;
+            const long long cnt = (long long)wk * nc;
+            double* Wst = slices > 1 ? WSb + (size_t)(t.stream == 1 ? 1 : 0) * max_slices * b * n : W;
+            // W = -V^T C (k-slices summed in slice order), Ym = -T^T W, C -= V Ym
+            if (launch_gemm_split<double>(wk, nc, mk, ks, VTk, wk, C, (int)lda, Wst, wk, cnt, st)) return LU_ERR_HIP;
+            if (slices > 1 && launch_qr_wsum(Wst, slices, cnt, W, st)) return LU_ERR_HIP;
+            if (launch_fill_zero(Ym, (size_t)cnt * sizeof(double), st)) return LU_ERR_HIP;
+            if (launch_gemm<double>(wk, nc, wk, TTk, wk, W, wk, Ym, wk, st)) return LU_ERR_HIP;
             if (launch_gemm<double>(mk, nc, wk, Vk, mk, Ym, wk, C, (int)lda, st)) return LU_ERR_HIP;  // C -= V Ym
         } else {
             return LU_ERR_UNSUPPORTED;
