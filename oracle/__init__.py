@@ -23,6 +23,10 @@ Contents
 * ``geqrf``: ctypes wrapper over ``qr_oracle.c`` -- plain FP64 Householder QR
   (geqr2 storage: R on and above the diagonal, reflectors below, tau);
   ``q_from`` builds Q explicitly from the reflectors.
+* ``gebrd_band``: ctypes wrapper over ``band_oracle.c`` -- plain FP64
+  two-sided reduction to upper band form (first stage of the SVD, the third
+  workload of Sec. 6); ``band_part`` extracts the band, ``band_uv`` builds the
+  orthogonal factors U, V from the stored reflectors (A = U B V^T).
 * ``mlp``: FP64 forward/backward/Adam of the schedule-selector network.
 """
 from __future__ import annotations
@@ -35,7 +39,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lu_oracle.c")
-_SRCS = [_SRC, os.path.join(_HERE, "chol_oracle.c"), os.path.join(_HERE, "qr_oracle.c")]
+_SRCS = [_SRC, os.path.join(_HERE, "chol_oracle.c"), os.path.join(_HERE, "qr_oracle.c"),
+         os.path.join(_HERE, "band_oracle.c")]
 _LIB = os.path.join(_HERE, "liblu_oracle.so")
 
 EPS64 = 2.0 ** -53
@@ -71,6 +76,9 @@ def _load():
                                      ctypes.c_int]
         lib.oracle_potrf.restype = ctypes.c_int
         lib.oracle_potrf.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
+        lib.oracle_gebrd_band.restype = ctypes.c_int
+        lib.oracle_gebrd_band.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                                          ctypes.c_void_p, ctypes.c_void_p]
         _lib = lib
     return _lib
 
@@ -151,6 +159,52 @@ def q_from(F: np.ndarray, tau: np.ndarray) -> np.ndarray:
         v[j + 1:] = F[j + 1:, j]
         Q = Q - tau[j] * np.outer(v, v @ Q)
     return Q
+
+
+def gebrd_band(A: np.ndarray, w: int):
+    """Two-sided reduction of the square matrix A to upper band form with
+    bandwidth w: returns (F, tauq, taup) in the storage band_oracle.c
+    describes."""
+    n = A.shape[0]
+    if A.shape[1] != n:
+        raise ValueError("square matrix expected")
+    F = np.array(A, dtype=np.float64, order="F", copy=True)
+    F, lda = _as_colmajor(F)
+    tauq = np.zeros(max(n, 1), dtype=np.float64)
+    taup = np.zeros(max(n, 1), dtype=np.float64)
+    rc = _load().oracle_gebrd_band(n, int(w), F.ctypes.data, max(lda, 1), tauq.ctypes.data, taup.ctypes.data)
+    if rc < 0:
+        raise ValueError("oracle_gebrd_band: illegal argument %d" % -rc)
+    return F, tauq[:n], taup[:n]
+
+
+def band_part(F: np.ndarray, w: int) -> np.ndarray:
+    """The band B of a reduced matrix: entries (i, j) with 0 <= j - i <= w."""
+    n = F.shape[0]
+    i, j = np.indices((n, n))
+    return np.where((j - i >= 0) & (j - i <= w), F, 0.0)
+
+
+def band_uv(F: np.ndarray, tauq: np.ndarray, taup: np.ndarray, w: int):
+    """U = H_0 H_1 ... (column reflectors) and V = G_0 G_1 ... (row
+    reflectors) of a band reduction, so that A = U B V^T."""
+    n = F.shape[0]
+    U = np.eye(n)
+    for j in range(n - 1, -1, -1):
+        v = np.zeros(n)
+        v[j] = 1.0
+        v[j + 1:] = F[j + 1:, j]
+        U = U - tauq[j] * np.outer(v, v @ U)
+    V = np.eye(n)
+    for r in range(n - 1, -1, -1):
+        c = (r // w) * w + w + (r % w)
+        if c >= n:
+            continue
+        v = np.zeros(n)
+        v[c] = 1.0
+        v[c + 1:] = F[r, c + 1:]
+        V = V - taup[r] * np.outer(v, v @ V)
+    return U, V
 
 
 def r_chol(A: np.ndarray, F: np.ndarray, matmul=None) -> float:
