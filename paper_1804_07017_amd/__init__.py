@@ -63,6 +63,7 @@ _SIGS = {
     "chol_solve": (_I, [_I, _I, _P, _I, _P, _I, _P]),
     "qr_factor": (_I, [_I, _I, _P, _I, _P, _P]),
     "qr_factor_ex": (_I, [_I, _I, _P, _I, _P, ctypes.POINTER(Schedule), _P]),
+    "band_reduce": (_I, [_I, _P, _I, _I, _P, _P, _P]),
     "lu_plan_panels": (_I, [_I, _I, _I, _I, ctypes.POINTER(_I), _I]),
     "lu_plan_build_panels": (_I, [_I, ctypes.POINTER(_I), _I, _I, ctypes.POINTER(PlanTask), _I]),
     "lu_k_panel": (_I, [_I, _I, _I, _P, _I, _P, _I, _P, _P]),
@@ -200,6 +201,13 @@ def qr_factor(A, tau, sched=None, stream=None):
     if sched is None:
         return load().qr_factor(m, n, _ptr(A), _ld(A), _ptr(tau), _stream(stream))
     return load().qr_factor_ex(m, n, _ptr(A), _ld(A), _ptr(tau), _sched(sched), _stream(stream))
+
+
+def band_reduce(A, w, tauq, taup, stream=None):
+    """Two-sided reduction of the square column-major device matrix A to upper
+    band form with bandwidth w in place; tauq, taup (n,) device."""
+    n = A.shape[0]
+    return load().band_reduce(n, _ptr(A), _ld(A), int(w), _ptr(tauq), _ptr(taup), _stream(stream))
 
 
 def lu_factor_info():

@@ -148,7 +148,9 @@ void release_all() {
         if (s->info) hipFree(s->info);
         Buffer* bufs[] = {&s->cand, &s->moves, &s->linv, &s->lh, &s->uh, &s->rs, &s->cs, &s->solve_moves, &s->flags,
                           &s->partial, &s->ir_r, &s->ir_x32, &s->ir_a32, &s->ir_a64, &s->ir_norms, &s->ir_ipiv,
-                          &s->ir_b, &s->qr_v, &s->qr_vt, &s->qr_t, &s->qr_tt, &s->qr_w, &s->qr_ws, &s->qr_ym, &s->qr_part};
+                          &s->ir_b, &s->qr_v, &s->qr_vt, &s->qr_t, &s->qr_tt, &s->qr_w, &s->qr_ws, &s->qr_ym, &s->qr_part,
+                          &s->band_z, &s->band_v, &s->band_vt, &s->band_t, &s->band_tt, &s->band_w,
+                          &s->band_y, &s->band_ws};
         for (Buffer* b : bufs) release(*b);
         delete s;
     }

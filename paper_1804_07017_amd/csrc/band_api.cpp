@@ -1,0 +1,144 @@
+// Two-sided reduction of a square matrix to upper band form (the first stage
+// of a two-stage SVD, the third workload of the paper's evaluation, Sec. 6).
+// Iteration k (columns and rows k .. k+kw-1):
+//   1. Householder QR of the column panel A[k:n, k:k+kw] (the QR panel kernel),
+//      then U_k^T = I - V T^T V^T applied from the left to A[k:n, k+kw:n]:
+//      W = -V^T C (k-sliced), Ym = -T^T W, C -= V Ym;
+//   2. the row panel A[k:k+w', c0:n] (c0 = k + w, w' = min(kw, n - c0)) is
+//      transposed into Z (n - c0 rows), factored by the same panel kernel (its
+//      QR is the panel's LQ: L = R^T, the same reflectors and tau) and written
+//      back; V_k = I - V T V^T is applied from the right to the rows below,
+//      D = A[k+w':n, c0:n]: W2 = -D V (k-sliced), Y2 = -W2 T, D -= Y2 V^T.
+// All products run on the trailing-update GEMM kernel; every step is ordered
+// on the caller's stream (no look-ahead).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "../../include/band.h"
+#include "kernels.hpp"
+#include "state.hpp"
+
+namespace lu {
+
+namespace {
+
+int band_execute(DeviceState* s, int n, double* A, long long lda, int w, double* tauq, double* taup,
+                 hipStream_t st) {
+    int rc;
+    const size_t nw = (size_t)n * w;
+    const int ks = s->qr_split_rows;
+    const int max_slices = (n + ks - 1) / ks;
+    if ((rc = ensure(s->band_z, nw * sizeof(double)))) return rc;
+    if ((rc = ensure(s->band_v, nw * sizeof(double)))) return rc;
+    if ((rc = ensure(s->band_vt, nw * sizeof(double)))) return rc;
+    if ((rc = ensure(s->band_t, (size_t)w * w * sizeof(double)))) return rc;
+    if ((rc = ensure(s->band_tt, (size_t)w * w * sizeof(double)))) return rc;
+    if ((rc = ensure(s->band_w, nw * sizeof(double)))) return rc;
+    if ((rc = ensure(s->band_y, nw * sizeof(double)))) return rc;
+    if (max_slices > 1 && (rc = ensure(s->band_ws, (size_t)max_slices * nw * sizeof(double)))) return rc;
+    if ((rc = ensure(s->qr_part, (size_t)kQrPartWords * sizeof(double)))) return rc;
+    double* Z = reinterpret_cast<double*>(s->band_z.ptr);
+    double* Vw = reinterpret_cast<double*>(s->band_v.ptr);
+    double* VT = reinterpret_cast<double*>(s->band_vt.ptr);
+    double* T = reinterpret_cast<double*>(s->band_t.ptr);
+    double* TT = reinterpret_cast<double*>(s->band_tt.ptr);
+    double* W = reinterpret_cast<double*>(s->band_w.ptr);
+    double* Y = reinterpret_cast<double*>(s->band_y.ptr);
+    double* WS = max_slices > 1 ? reinterpret_cast<double*>(s->band_ws.ptr) : nullptr;
+
+    // one panel factorization (m x pw at P, leading dimension ld) into T / tau
+    auto panel = [&](double* P, long long ld, int m, int pw, double* tau) -> int {
+        QrPanelArgs pa;
+        pa.A = P;
+        pa.lda = ld;
+        pa.m = m;
+        pa.w = pw;
+        pa.tau = tau;
+        pa.T = T;
+        pa.part = reinterpret_cast<double*>(s->qr_part.ptr);
+        pa.sync = s->sync + 2 * s->sync_slot;
+        pa.sync_next = s->sync + 2 * (1 - s->sync_slot);
+        s->sync_slot = 1 - s->sync_slot;
+        pa.spin_limit = s->spin_limit;
+        const int wgs = (m + 1023) / 1024;
+        if (wgs > 64 || wgs > s->num_cus) return LU_ERR_UNSUPPORTED;
+        // T's strictly lower part stays zero: the right-hand update multiplies by T itself
+        if (launch_fill_zero(T, (size_t)pw * pw * sizeof(double), st)) return LU_ERR_HIP;
+        if (launch_qr_panel(pa, wgs, st)) return LU_ERR_HIP;
+        if (launch_qr_prep(P, ld, m, pw, T, Vw, VT, TT, st)) return LU_ERR_HIP;
+        return 0;
+    };
+
+    for (int k = 0; k < n; k += w) {
+        const int kw = std::min(w, n - k);
+        const int mk = n - k;
+        // 1. column panel and the left-hand update of the columns right of it
+        if ((rc = panel(A + k + (long long)k * lda, lda, mk, kw, tauq + k))) return rc;
+        const int nc = n - k - kw;
+        if (nc > 0) {
+            double* C = A + k + (long long)(k + kw) * lda;
+            const long long cnt = (long long)kw * nc;
+            const int slices = (mk + ks - 1) / ks;
+            double* Wst = slices > 1 ? WS : W;
+            if (launch_gemm_split<double>(kw, nc, mk, ks, VT, kw, C, (int)lda, Wst, kw, cnt, st)) return LU_ERR_HIP;
+            if (slices > 1 && launch_qr_wsum(Wst, slices, cnt, W, st)) return LU_ERR_HIP;
+            if (launch_fill_zero(Y, (size_t)cnt * sizeof(double), st)) return LU_ERR_HIP;
+            if (launch_gemm<double>(kw, nc, kw, TT, kw, W, kw, Y, kw, st)) return LU_ERR_HIP;
+            if (launch_gemm<double>(mk, nc, kw, Vw, mk, Y, kw, C, (int)lda, st)) return LU_ERR_HIP;
+        }
+        // 2. row panel (as the QR of its transpose) and the right-hand update
+        const int c0 = k + w;
+        if (c0 >= n) continue;
+        const int np = n - c0;
+        const int wp = std::min(kw, np);
+        double* R = A + k + (long long)c0 * lda;
+        if (launch_transpose_f64(R, lda, wp, np, Z, np, st)) return LU_ERR_HIP;
+        if ((rc = panel(Z, np, np, wp, taup + k))) return rc;
+        if (launch_transpose_f64(Z, np, np, wp, R, lda, st)) return LU_ERR_HIP;
+        const int md = n - k - wp;
+        if (md > 0) {
+            double* D = A + (k + wp) + (long long)c0 * lda;
+            const long long cnt = (long long)md * wp;
+            const int slices = (np + ks - 1) / ks;
+            double* Wst = slices > 1 ? WS : W;
+            if (launch_gemm_split<double>(md, wp, np, ks, D, (int)lda, Vw, np, Wst, md, cnt, st)) return LU_ERR_HIP;
+            if (slices > 1 && launch_qr_wsum(Wst, slices, cnt, W, st)) return LU_ERR_HIP;
+            if (launch_fill_zero(Y, (size_t)cnt * sizeof(double), st)) return LU_ERR_HIP;
+            if (launch_gemm<double>(md, wp, wp, W, md, T, wp, Y, md, st)) return LU_ERR_HIP;      // Y2 = -W2 T
+            if (launch_gemm<double>(md, np, wp, Y, md, VT, wp, D, (int)lda, st)) return LU_ERR_HIP; // D -= Y2 V^T
+        }
+    }
+    return 0;
+}
+
+}  // namespace
+
+int band_reduce_impl(int n, double* A, int lda, int w, double* tauq, double* taup, hipStream_t stream) {
+    if (n < 0) return -1;
+    if (!A && n > 0) return -2;
+    if (lda < std::max(1, n)) return -3;
+    if (w < 1 || w > kQrMaxPanelW) return -4;
+    if (!tauq && n > 0) return -5;
+    if (!taup && n > 0) return -6;
+    if (n == 0) return 0;
+    int err;
+    DeviceState* s = device_state(&err);
+    if (!s) return err;
+    if ((long long)n > 1024LL * std::min(64, s->num_cus)) return LU_ERR_UNSUPPORTED;
+    if (launch_fill_zero(s->info, sizeof(int), stream)) return LU_ERR_HIP;
+    if (launch_fill_zero(taup, (size_t)n * sizeof(double), stream)) return LU_ERR_HIP;
+    s->last_stream = stream;
+    s->last_info = s->info;
+    return band_execute(s, n, A, lda, w, tauq, taup, stream);
+}
+
+}  // namespace lu
+
+extern "C" {
+
+int band_reduce(int n, double* A, int lda, int w, double* tauq, double* taup, hipStream_t stream) {
+    return lu::band_reduce_impl(n, A, lda, w, tauq, taup, stream);
+}
+
+}  // extern "C"

@@ -120,7 +120,8 @@ struct QrPanelArgs {
     long long spin_limit;
 };
 // workspace of the QR panel: per-group partial sums and the block-phase W
-constexpr int kQrPartWords = 128 + 64 * 16 + 64 * 16 * 256 + 16 * 256;
+constexpr int kQrMaxPanelW = 384;
+constexpr int kQrPartWords = 128 + 64 * 16 + 64 * 16 * kQrMaxPanelW + 16 * kQrMaxPanelW;
 int launch_qr_panel(const QrPanelArgs& args, int wgs, hipStream_t stream);
 // Vw (m x w, ld m) and VT (w x m, ld w): the panel's unit-lower V, explicit;
 // TT = T^T (w x w, ld w)
@@ -128,6 +129,9 @@ int launch_qr_prep(const double* A, long long lda, int m, int w, const double* T
                    double* TT, hipStream_t stream);
 // W = sum of the S k-slices Wp[s * count ...] in slice order
 int launch_qr_wsum(const double* Wp, int S, long long count, double* W, hipStream_t stream);
+// dst (cols x rows, ld ldd) = src^T, src rows x cols with ld lds
+int launch_transpose_f64(const double* src, long long lds, int rows, int cols, double* dst, long long ldd,
+                         hipStream_t stream);
 
 // ---- solves and refinement (solve.hip) ----
 // x (n x nrhs, ld) <- P x using per-chunk moves from launch_chunk_moves

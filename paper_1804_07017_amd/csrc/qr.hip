@@ -43,7 +43,7 @@ namespace {
 constexpr int kQrThreads = 256;
 constexpr int kQrRows = 4;          // panel rows per thread
 constexpr int kQrGroupRows = kQrThreads * kQrRows;
-constexpr int kQrMaxW = 256;
+constexpr int kQrMaxW = kQrMaxPanelW;   // the widest panel: QR block size, band width
 constexpr int kQrNB = 16;           // columns of an inner block (held in registers)
 constexpr int kQrWaves = kQrThreads / kWave;
 constexpr int kQrWc = 4;                         // columns per chunk of the block phase

@@ -19,7 +19,7 @@ def _declared_symbols():
             continue
         txt = open(os.path.join(ROOT, "include", h)).read()
         txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-        for m in re.finditer(r"^\s*(?:int|void)\s+((?:lu|chol|qr)_\w+)\s*\(", txt, flags=re.M):
+        for m in re.finditer(r"^\s*(?:int|void)\s+((?:lu|chol|qr|band)_\w+)\s*\(", txt, flags=re.M):
             names.add(m.group(1))
     return names
 
