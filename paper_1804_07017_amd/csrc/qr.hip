@@ -10,7 +10,8 @@
 // threads each), group g owning the 1024-row block starting at g*1024 and
 // thread t its rows g*1024 + t + s*256 (s < 4).  The panel is processed in
 // inner blocks of 16 columns that each thread holds in registers for its rows.
-// Per column J of an inner block, with two device-wide barriers:
+// Per column J of an inner block, with two device-wide barriers (without
+// cache maintenance: the few words exchanged use device-scope atomics):
 //   1. each group's partial sum of squares below the diagonal (the owner of
 //      row J also publishes the diagonal entry) -> barrier;
 //   2. every group forms the same reflector (beta, tau, 1/(alpha - beta)) from
@@ -31,8 +32,6 @@
 // sum runs in a fixed order (rows s, lanes by butterfly, waves, then groups),
 // so the factorization of a given panel is bitwise the same whatever the
 // schedule.
-#include <utility>
-
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -93,6 +92,8 @@ struct QrShared {
     double Ys[kQrNB][kQrMaxW];              // T_b^T W of the columns right of the block
     double Us[kQrMaxW][kQrNB];              // (V^T V_b) T_b of the columns left of it
     double sc[4];                           // tau, scal, beta
+    double pss[65];                         // the groups' sums of squares, [64] the diagonal entry
+    double pdot[64 * kQrNB];                // the groups' dot products
 };
 
 // Where a thread is: its group, lanes and first row.
@@ -100,35 +101,64 @@ struct QrPos {
     int tid, lane, wave, g, P, row0;
 };
 
-// Column cb + JJ of the inner block held in X (steps 1-4 of the header); false
-// when a barrier timed out.
-template <int JJ>
+// The per-column exchange words (partial sums, the diagonal entry) are read
+// and written with device-scope atomics, which bypass the per-XCD L2, so the
+// two barriers of a column need no cache write-back or invalidation.
+__device__ __forceinline__ void st_dev(double* p, double v) {
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_dev(const double* p) {
+    return __longlong_as_double((long long)__hip_atomic_load(reinterpret_cast<const unsigned long long*>(p),
+                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// One slot of the inner block's register ring forward: slot p takes slot p+1's
+// column, slot 15 the column of slot 0.
+__device__ __forceinline__ void qr_rotate(double (&X)[kQrRows][kQrNB]) {
+#pragma unroll
+    for (int s = 0; s < kQrRows; ++s) {
+        const double t = X[s][0];
+#pragma unroll
+        for (int q = 0; q + 1 < kQrNB; ++q) X[s][q] = X[s][q + 1];
+        X[s][kQrNB - 1] = t;
+    }
+}
+
+// Column J = cb + jj of the inner block (steps 1-4 of the header); false when
+// a barrier timed out.  The block is a ring of 16 register slots: on entry
+// slot 0 holds column J, slot p (p < 16 - jj) column J + p and slot 16 - jj + l
+// the finished column cb + l (l < jj); on return the ring has moved one slot
+// forward.  One copy of this code serves every column (static slot indices).
 __device__ __forceinline__ bool qr_column(double (&X)[kQrRows][kQrNB], QrShared& sh, const QrPanelArgs& a,
-                                          const QrPos& p, int cb, int nbw, unsigned& epoch) {
-    if (JJ >= nbw) return true;
+                                          const QrPos& p, int cb, int nbw, int jj, unsigned& epoch) {
     const int tid = p.tid, lane = p.lane, wave = p.wave, g = p.g, P = p.P, row0 = p.row0;
     const int m = a.m;
     double* part = a.part;
-    const int J = cb + JJ;
+    const int J = cb + jj;
     // 1. partial sum of squares below the diagonal; the owner of row J
     //    publishes the diagonal entry
     double ss = 0.0;
 #pragma unroll
     for (int s = 0; s < kQrRows; ++s) {
         const int i = row0 + s * kQrThreads;
-        if (i > J && i < m) ss = ss + X[s][JJ] * X[s][JJ];
-        if (i == J) part[kPartAlpha] = X[s][JJ];
+        if (i > J && i < m) ss = ss + X[s][0] * X[s][0];
+        if (i == J) st_dev(&part[kPartAlpha], X[s][0]);
     }
     ss = wave_sum(ss);
     if (lane == 0) sh.rw[wave][0] = ss;
     __syncthreads();
-    if (tid == 0) part[kPartSs + g] = (sh.rw[0][0] + sh.rw[1][0]) + (sh.rw[2][0] + sh.rw[3][0]);
-    if (grid_barrier(a.sync, a.sync + 1, ++epoch, a.spin_limit)) return false;
-    // 2. the reflector, identical in every group
+    if (tid == 0) st_dev(&part[kPartSs + g], (sh.rw[0][0] + sh.rw[1][0]) + (sh.rw[2][0] + sh.rw[3][0]));
+    if (grid_barrier(a.sync, a.sync + 1, ++epoch, a.spin_limit, false)) return false;
+    // 2. the reflector, identical in every group (the partials loaded in
+    //    parallel, summed in group order)
+    if (tid < P) sh.pss[tid] = ld_dev(&part[kPartSs + tid]);
+    if (tid == kQrThreads - 1) sh.pss[64] = ld_dev(&part[kPartAlpha]);
+    __syncthreads();
     if (tid == 0) {
         double sig = 0.0;
-        for (int q = 0; q < P; ++q) sig = sig + part[kPartSs + q];
-        const double alpha = part[kPartAlpha];
+        for (int q = 0; q < P; ++q) sig = sig + sh.pss[q];
+        const double alpha = sh.pss[64];
         double tau = 0.0, scal = 1.0, beta = alpha;
         if (sig != 0.0) {
             const double nrm = sqrt(alpha * alpha + sig);
@@ -147,28 +177,28 @@ __device__ __forceinline__ bool qr_column(double (&X)[kQrRows][kQrNB], QrShared&
         v[s] = 0.0;
         if (i == J) {
             v[s] = 1.0;
-            X[s][JJ] = sh.sc[2];
+            X[s][0] = sh.sc[2];
         } else if (i > J && i < m) {
-            double x = X[s][JJ];
+            double x = X[s][0];
             if (tau != 0.0) {
                 x = x * scal;
-                X[s][JJ] = x;
+                X[s][0] = x;
             }
             v[s] = x;
         }
     }
-    // 3. partial dot products of v with the block's other columns
+    // 3. partial dot products of v with the other slots (the columns right of J
+    //    for the update, the finished ones for T_b), rows >= J
     if (tau != 0.0) {
         double d[kQrNB];
+        d[0] = 0.0;
 #pragma unroll
-        for (int c = 0; c < kQrNB; ++c) {
+        for (int c = 1; c < kQrNB; ++c) {
             double acc = 0.0;
-            if (c != JJ) {
 #pragma unroll
-                for (int s = 0; s < kQrRows; ++s) {
-                    const int i = row0 + s * kQrThreads;
-                    if (i >= J && i < m) acc = acc + v[s] * X[s][c];
-                }
+            for (int s = 0; s < kQrRows; ++s) {
+                const int i = row0 + s * kQrThreads;
+                if (i >= J && i < m) acc = acc + v[s] * X[s][c];
             }
             d[c] = acc;
         }
@@ -176,47 +206,47 @@ __device__ __forceinline__ bool qr_column(double (&X)[kQrRows][kQrNB], QrShared&
         if ((lane & (kWave / kQrNB - 1)) == 0) sh.rw[wave][lane / (kWave / kQrNB)] = dl;
     }
     __syncthreads();
-    if (tau != 0.0 && tid < nbw && tid != JJ)
-        part[kPartDot + g * kQrNB + tid] = (sh.rw[0][tid] + sh.rw[1][tid]) + (sh.rw[2][tid] + sh.rw[3][tid]);
-    if (grid_barrier(a.sync, a.sync + 1, ++epoch, a.spin_limit)) return false;
-    // 4. sums in group order; the block's columns right of J; T_b column JJ
+    if (tau != 0.0 && tid >= 1 && tid < kQrNB)
+        st_dev(&part[kPartDot + g * kQrNB + tid], (sh.rw[0][tid] + sh.rw[1][tid]) + (sh.rw[2][tid] + sh.rw[3][tid]));
+    if (grid_barrier(a.sync, a.sync + 1, ++epoch, a.spin_limit, false)) return false;
+    // 4. sums in group order; the columns right of J; T_b column jj
+    if (tau != 0.0)
+        for (int e = tid; e < P * kQrNB; e += kQrThreads) sh.pdot[e] = ld_dev(&part[kPartDot + e]);
+    __syncthreads();
     if (tid < kQrNB) {
         double sum = 0.0;
-        if (tau != 0.0 && tid < nbw && tid != JJ)
-            for (int q = 0; q < P; ++q) sum = sum + part[kPartDot + q * kQrNB + tid];
+        if (tau != 0.0 && tid >= 1)
+            for (int q = 0; q < P; ++q) sum = sum + sh.pdot[q * kQrNB + tid];
         sh.dsum[tid] = sum;
     }
     __syncthreads();
     if (tau != 0.0) {
+        const int nright = nbw - jj;          // slots 1 .. nright-1 hold the columns right of J
 #pragma unroll
-        for (int c = JJ + 1; c < kQrNB; ++c) {
-            const double t = -tau * sh.dsum[c];
+        for (int c = 1; c < kQrNB; ++c) {
+            if (c < nright) {
+                const double t = -tau * sh.dsum[c];
 #pragma unroll
-            for (int s = 0; s < kQrRows; ++s) {
-                const int i = row0 + s * kQrThreads;
-                if (i >= J && i < m) X[s][c] = X[s][c] + v[s] * t;
+                for (int s = 0; s < kQrRows; ++s) {
+                    const int i = row0 + s * kQrThreads;
+                    if (i >= J && i < m) X[s][c] = X[s][c] + v[s] * t;
+                }
             }
         }
     }
-    if (tid < JJ) {
+    if (tid < jj) {
         double acc = 0.0;
         if (tau != 0.0)
-            for (int l = tid; l < JJ; ++l) acc = acc + sh.Tb[tid][l] * sh.dsum[l];
-        sh.Tb[tid][JJ] = -tau * acc;
+            for (int l = tid; l < jj; ++l) acc = acc + sh.Tb[tid][l] * sh.dsum[kQrNB - jj + l];
+        sh.Tb[tid][jj] = -tau * acc;
     }
     if (tid == 0) {
-        sh.Tb[JJ][JJ] = tau;
+        sh.Tb[jj][jj] = tau;
         if (g == 0) a.tau[J] = tau;
     }
-    __syncthreads();             // rw, sc, dsum and Tb are rewritten by the next column
+    __syncthreads();             // rw, sc, pss, pdot, dsum and Tb are rewritten by the next column
+    qr_rotate(X);
     return true;
-}
-
-template <int... Js>
-__device__ __forceinline__ bool qr_columns(std::integer_sequence<int, Js...>, double (&X)[kQrRows][kQrNB],
-                                           QrShared& sh, const QrPanelArgs& a, const QrPos& p, int cb, int nbw,
-                                           unsigned& epoch) {
-    return (qr_column<Js>(X, sh, a, p, cb, nbw, epoch) && ...);
 }
 
 __global__ __launch_bounds__(kQrThreads) void qr_panel_kernel(QrPanelArgs a) {
@@ -249,7 +279,11 @@ __global__ __launch_bounds__(kQrThreads) void qr_panel_kernel(QrPanelArgs a) {
 
         {
             const QrPos pos{tid, lane, wave, g, P, row0};
-            if (!qr_columns(std::make_integer_sequence<int, kQrNB>{}, X, sh, a, pos, cb, nbw, epoch)) return;
+#pragma unroll 1
+            for (int jj = 0; jj < nbw; ++jj)
+                if (!qr_column(X, sh, a, pos, cb, nbw, jj, epoch)) return;
+#pragma unroll 1
+            for (int jj = nbw; jj < kQrNB; ++jj) qr_rotate(X);   // slot c holds column cb + c again
         }
 
         // the inner block's R and V back to memory; then X <- V_b (unit lower, 0 outside)
@@ -317,25 +351,38 @@ __global__ __launch_bounds__(kQrThreads) void qr_panel_kernel(QrPanelArgs a) {
             const int c = e / kQrNB;
             if (c >= cb && c < cb + kQrNB) continue;
             double sum = 0.0;
+#pragma unroll 8
             for (int q = 0; q < P; ++q) sum = sum + part[kPartW + (size_t)q * ww + e];
             part[kPartWs + e] = sum;
         }
         if (grid_barrier(a.sync, a.sync + 1, ++epoch, a.spin_limit)) return;
-        // 7. Y = T_b^T W for the columns right of the block; their update
+        // 7. Y = T_b^T W for the columns right of the block (then their
+        //    update) and U = (V^T V_b) T_b for the columns left of it; one
+        //    column of W per thread
         const double* Ws = part + kPartWs;
-        const int c1 = cb + kQrNB, nr = w - c1;
-        for (int e = tid; e < kQrNB * (nr > 0 ? nr : 0); e += kQrThreads) {
-            const int l = e % kQrNB, c = e / kQrNB;
-            double acc = 0.0;
-            for (int p = 0; p <= l; ++p) acc = acc + Tb[p][l] * Ws[p + kQrNB * (c1 + c)];
-            Ys[l][c] = acc;
-        }
-        // (V^T V_b) T_b for the columns left of it
-        for (int e = tid; e < cb * kQrNB; e += kQrThreads) {
-            const int q = e % kQrNB, c = e / kQrNB;
-            double acc = 0.0;
-            for (int l = 0; l <= q; ++l) acc = acc + Ws[l + kQrNB * c] * Tb[l][q];
-            Us[c][q] = acc;
+        const int c1 = cb + kQrNB;
+        for (int c = tid; c < w; c += kQrThreads) {
+            if (c >= cb && c < c1) continue;
+            double wv[kQrNB];
+#pragma unroll
+            for (int p = 0; p < kQrNB; ++p) wv[p] = Ws[p + kQrNB * c];
+            if (c >= c1) {
+#pragma unroll
+                for (int l = 0; l < kQrNB; ++l) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int p = 0; p <= l; ++p) acc = acc + Tb[p][l] * wv[p];
+                    Ys[l][c - c1] = acc;
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < kQrNB; ++q) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int l = 0; l <= q; ++l) acc = acc + wv[l] * Tb[l][q];
+                    Us[c][q] = acc;
+                }
+            }
         }
         __syncthreads();
         for (int c00 = c1; c00 < w; c00 += 4) {
@@ -361,12 +408,27 @@ __global__ __launch_bounds__(kQrThreads) void qr_panel_kernel(QrPanelArgs a) {
                 }
             }
         }
-        // T[0:cb, block] = -T[0:cb, 0:cb] U, rows of T spread over the groups
-        for (int e = g * kQrThreads + tid; e < cb * nbw; e += kQrThreads * P) {
-            const int r = e % cb, q = e / cb;
-            double acc = 0.0;
-            for (int c = r; c < cb; ++c) acc = acc + a.T[r + (long long)c * w] * Us[c][q];
-            a.T[r + (long long)(cb + q) * w] = -acc;
+        // T[0:cb, block] = -T[0:cb, 0:cb] U: T's rows in runs of 64, one run per
+        // wave (lane = row, so each column of T is read coalesced), all 16
+        // block columns per lane; the sum over c runs in column order
+        for (int run = g * kQrWaves + wave; run * kWave < cb; run += P * kQrWaves) {
+            const int r = run * kWave + lane;
+            const int rr = min(r, cb - 1);
+            double acc[kQrNB];
+#pragma unroll
+            for (int q = 0; q < kQrNB; ++q) acc[q] = 0.0;
+#pragma unroll 4
+            for (int c = run * kWave; c < cb; ++c) {
+                const double tv = a.T[rr + (long long)c * w];
+                const double t = r <= c ? tv : 0.0;          // T is upper triangular
+#pragma unroll
+                for (int q = 0; q < kQrNB; ++q) acc[q] = acc[q] + t * Us[c][q];
+            }
+            if (r < cb) {
+#pragma unroll
+                for (int q = 0; q < kQrNB; ++q)
+                    if (q < nbw) a.T[r + (long long)(cb + q) * w] = -acc[q];
+            }
         }
         __syncthreads();                     // Tb, Ys and Us are rewritten by the next block
     }
