@@ -9,8 +9,11 @@
 //      QR is the panel's LQ: L = R^T, the same reflectors and tau) and written
 //      back; V_k = I - V T V^T is applied from the right to the rows below,
 //      D = A[k+w':n, c0:n]: W2 = -D V (k-sliced), Y2 = -W2 T, D -= Y2 V^T.
-// All products run on the trailing-update GEMM kernel; every step is ordered
-// on the caller's stream (no look-ahead).
+// All products run on the trailing-update GEMM kernel.  Look-ahead (Sec. 4
+// applied to the two-sided reduction): the right-hand update of iteration k
+// writes the next column panel's columns first; that panel is then factored
+// on the panel stream while the rest of the update runs on the caller's
+// stream, and iteration k + 1 joins it before its left-hand update.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,33 +32,39 @@ int band_execute(DeviceState* s, int n, double* A, long long lda, int w, double*
     const size_t nw = (size_t)n * w;
     const int ks = s->qr_split_rows;
     const int max_slices = (n + ks - 1) / ks;
+    // two operand sets: the column panels' (left) and the row panels' (right),
+    // so that a column panel factored ahead never overwrites what the running
+    // right-hand update reads
     if ((rc = ensure(s->band_z, nw * sizeof(double)))) return rc;
-    if ((rc = ensure(s->band_v, nw * sizeof(double)))) return rc;
-    if ((rc = ensure(s->band_vt, nw * sizeof(double)))) return rc;
-    if ((rc = ensure(s->band_t, (size_t)w * w * sizeof(double)))) return rc;
-    if ((rc = ensure(s->band_tt, (size_t)w * w * sizeof(double)))) return rc;
+    if ((rc = ensure(s->band_v, 2 * nw * sizeof(double)))) return rc;
+    if ((rc = ensure(s->band_vt, 2 * nw * sizeof(double)))) return rc;
+    if ((rc = ensure(s->band_t, 2 * (size_t)w * w * sizeof(double)))) return rc;
+    if ((rc = ensure(s->band_tt, 2 * (size_t)w * w * sizeof(double)))) return rc;
     if ((rc = ensure(s->band_w, nw * sizeof(double)))) return rc;
     if ((rc = ensure(s->band_y, nw * sizeof(double)))) return rc;
     if (max_slices > 1 && (rc = ensure(s->band_ws, (size_t)max_slices * nw * sizeof(double)))) return rc;
     if ((rc = ensure(s->qr_part, (size_t)kQrPartWords * sizeof(double)))) return rc;
+    if ((rc = ensure_events(s, 2 * (size_t)((n + w - 1) / w) + 4))) return rc;
+    struct Ops { double *Vw, *VT, *T, *TT; };
+    Ops L{reinterpret_cast<double*>(s->band_v.ptr), reinterpret_cast<double*>(s->band_vt.ptr),
+          reinterpret_cast<double*>(s->band_t.ptr), reinterpret_cast<double*>(s->band_tt.ptr)};
+    Ops R{L.Vw + nw, L.VT + nw, L.T + (size_t)w * w, L.TT + (size_t)w * w};
     double* Z = reinterpret_cast<double*>(s->band_z.ptr);
-    double* Vw = reinterpret_cast<double*>(s->band_v.ptr);
-    double* VT = reinterpret_cast<double*>(s->band_vt.ptr);
-    double* T = reinterpret_cast<double*>(s->band_t.ptr);
-    double* TT = reinterpret_cast<double*>(s->band_tt.ptr);
     double* W = reinterpret_cast<double*>(s->band_w.ptr);
     double* Y = reinterpret_cast<double*>(s->band_y.ptr);
     double* WS = max_slices > 1 ? reinterpret_cast<double*>(s->band_ws.ptr) : nullptr;
+    const int ring = (int)s->events.size();
+    auto next_event = [&]() { hipEvent_t e = s->events[s->ev_next]; s->ev_next = (s->ev_next + 1) % ring; return e; };
 
-    // one panel factorization (m x pw at P, leading dimension ld) into T / tau
-    auto panel = [&](double* P, long long ld, int m, int pw, double* tau) -> int {
+    // one panel factorization (m x pw at P, leading dimension ld) into o / tau on stream q
+    auto panel = [&](double* P, long long ld, int m, int pw, double* tau, const Ops& o, hipStream_t q) -> int {
         QrPanelArgs pa;
         pa.A = P;
         pa.lda = ld;
         pa.m = m;
         pa.w = pw;
         pa.tau = tau;
-        pa.T = T;
+        pa.T = o.T;
         pa.part = reinterpret_cast<double*>(s->qr_part.ptr);
         pa.sync = s->sync + 2 * s->sync_slot;
         pa.sync_next = s->sync + 2 * (1 - s->sync_slot);
@@ -64,51 +73,82 @@ int band_execute(DeviceState* s, int n, double* A, long long lda, int w, double*
         const int wgs = (m + 1023) / 1024;
         if (wgs > 64 || wgs > s->num_cus) return LU_ERR_UNSUPPORTED;
         // T's strictly lower part stays zero: the right-hand update multiplies by T itself
-        if (launch_fill_zero(T, (size_t)pw * pw * sizeof(double), st)) return LU_ERR_HIP;
-        if (launch_qr_panel(pa, wgs, st)) return LU_ERR_HIP;
-        if (launch_qr_prep(P, ld, m, pw, T, Vw, VT, TT, st)) return LU_ERR_HIP;
+        if (launch_fill_zero(o.T, (size_t)pw * pw * sizeof(double), q)) return LU_ERR_HIP;
+        if (launch_qr_panel(pa, wgs, q)) return LU_ERR_HIP;
+        if (launch_qr_prep(P, ld, m, pw, o.T, o.Vw, o.VT, o.TT, q)) return LU_ERR_HIP;
         return 0;
     };
 
+    // look-ahead: the column panel of the next iteration is factored on the
+    // panel stream once the right-hand update has written its columns, while
+    // the rest of that update runs on the caller's stream
+    hipStream_t ps = s->panel_stream;
+    hipEvent_t ev0 = next_event();
+    LU_HIP(hipEventRecord(ev0, st));
+    LU_HIP(hipStreamWaitEvent(ps, ev0, 0));
+    if ((rc = panel(A, lda, n, std::min(w, n), tauq, L, st))) return rc;
+    hipEvent_t pending = nullptr;              // the column panel factored ahead, not yet joined
     for (int k = 0; k < n; k += w) {
         const int kw = std::min(w, n - k);
         const int mk = n - k;
-        // 1. column panel and the left-hand update of the columns right of it
-        if ((rc = panel(A + k + (long long)k * lda, lda, mk, kw, tauq + k))) return rc;
+        if (pending) {
+            LU_HIP(hipStreamWaitEvent(st, pending, 0));
+            pending = nullptr;
+        }
+        // 1. the left-hand update of the columns right of the column panel
         const int nc = n - k - kw;
         if (nc > 0) {
             double* C = A + k + (long long)(k + kw) * lda;
             const long long cnt = (long long)kw * nc;
             const int slices = (mk + ks - 1) / ks;
             double* Wst = slices > 1 ? WS : W;
-            if (launch_gemm_split<double>(kw, nc, mk, ks, VT, kw, C, (int)lda, Wst, kw, cnt, st)) return LU_ERR_HIP;
+            if (launch_gemm_split<double>(kw, nc, mk, ks, L.VT, kw, C, (int)lda, Wst, kw, cnt, st)) return LU_ERR_HIP;
             if (slices > 1 && launch_qr_wsum(Wst, slices, cnt, W, st)) return LU_ERR_HIP;
             if (launch_fill_zero(Y, (size_t)cnt * sizeof(double), st)) return LU_ERR_HIP;
-            if (launch_gemm<double>(kw, nc, kw, TT, kw, W, kw, Y, kw, st)) return LU_ERR_HIP;
-            if (launch_gemm<double>(mk, nc, kw, Vw, mk, Y, kw, C, (int)lda, st)) return LU_ERR_HIP;
+            if (launch_gemm<double>(kw, nc, kw, L.TT, kw, W, kw, Y, kw, st)) return LU_ERR_HIP;
+            if (launch_gemm<double>(mk, nc, kw, L.Vw, mk, Y, kw, C, (int)lda, st)) return LU_ERR_HIP;
         }
         // 2. row panel (as the QR of its transpose) and the right-hand update
         const int c0 = k + w;
         if (c0 >= n) continue;
         const int np = n - c0;
         const int wp = std::min(kw, np);
-        double* R = A + k + (long long)c0 * lda;
-        if (launch_transpose_f64(R, lda, wp, np, Z, np, st)) return LU_ERR_HIP;
-        if ((rc = panel(Z, np, np, wp, taup + k))) return rc;
-        if (launch_transpose_f64(Z, np, np, wp, R, lda, st)) return LU_ERR_HIP;
+        double* Rp = A + k + (long long)c0 * lda;
+        if (launch_transpose_f64(Rp, lda, wp, np, Z, np, st)) return LU_ERR_HIP;
+        if ((rc = panel(Z, np, np, wp, taup + k, R, st))) return rc;
+        if (launch_transpose_f64(Z, np, np, wp, Rp, lda, st)) return LU_ERR_HIP;
         const int md = n - k - wp;
+        const int kn = std::min(w, n - c0);    // width of the next column panel (its columns start at c0)
         if (md > 0) {
             double* D = A + (k + wp) + (long long)c0 * lda;
             const long long cnt = (long long)md * wp;
             const int slices = (np + ks - 1) / ks;
             double* Wst = slices > 1 ? WS : W;
-            if (launch_gemm_split<double>(md, wp, np, ks, D, (int)lda, Vw, np, Wst, md, cnt, st)) return LU_ERR_HIP;
+            if (launch_gemm_split<double>(md, wp, np, ks, D, (int)lda, R.Vw, np, Wst, md, cnt, st)) return LU_ERR_HIP;
             if (slices > 1 && launch_qr_wsum(Wst, slices, cnt, W, st)) return LU_ERR_HIP;
             if (launch_fill_zero(Y, (size_t)cnt * sizeof(double), st)) return LU_ERR_HIP;
-            if (launch_gemm<double>(md, wp, wp, W, md, T, wp, Y, md, st)) return LU_ERR_HIP;      // Y2 = -W2 T
-            if (launch_gemm<double>(md, np, wp, Y, md, VT, wp, D, (int)lda, st)) return LU_ERR_HIP; // D -= Y2 V^T
+            if (launch_gemm<double>(md, wp, wp, W, md, R.T, wp, Y, md, st)) return LU_ERR_HIP;       // Y2 = -W2 T
+            // D -= Y2 V^T: the next column panel's columns first (the same
+            // per-element operations as one product over all columns)
+            if (launch_gemm<double>(md, kn, wp, Y, md, R.VT, wp, D, (int)lda, st)) return LU_ERR_HIP;
+        }
+        // the next column panel ahead, on the panel stream
+        {
+            hipEvent_t ready = next_event();
+            LU_HIP(hipEventRecord(ready, st));
+            LU_HIP(hipStreamWaitEvent(ps, ready, 0));
+            const int k1 = k + w;
+            if ((rc = panel(A + k1 + (long long)k1 * lda, lda, n - k1, kn, tauq + k1, L, ps))) return rc;
+            pending = next_event();
+            LU_HIP(hipEventRecord(pending, ps));
+        }
+        if (md > 0 && np > kn) {
+            double* D = A + (k + wp) + (long long)c0 * lda;
+            if (launch_gemm<double>(md, np - kn, wp, Y, md, R.VT + (size_t)kn * wp, wp, D + (long long)kn * lda,
+                                    (int)lda, st)) return LU_ERR_HIP;
         }
     }
+    if (pending) LU_HIP(hipStreamWaitEvent(st, pending, 0));
     return 0;
 }
 

@@ -45,7 +45,7 @@ constexpr int kQrGroupRows = kQrThreads * kQrRows;
 constexpr int kQrMaxW = kQrMaxPanelW;   // the widest panel: QR block size, band width
 constexpr int kQrNB = 16;           // columns of an inner block (held in registers)
 constexpr int kQrWaves = kQrThreads / kWave;
-constexpr int kQrWc = 4;                         // columns per chunk of the block phase
+constexpr int kQrWc = 2;                         // columns per chunk of the block phase
 constexpr int kQrWv = kQrWc * kQrNB;             // values per lane per chunk
 constexpr int kQrRound = 512 / kQrWv;            // chunks per LDS round
 // partial-sum workspace (doubles)
@@ -310,18 +310,28 @@ __global__ __launch_bounds__(kQrThreads) void qr_panel_kernel(QrPanelArgs a) {
         double* Wp = part + kPartW + (size_t)g * ww;
         const int nleft = cb / kQrWc, nright = (w - (cb + kQrNB) + kQrWc - 1) / kQrWc;
         const int nch = nleft + (nright > 0 ? nright : 0);
+        auto chunk_col = [&](int ch) { return ch < nleft ? kQrWc * ch : cb + kQrNB + kQrWc * (ch - nleft); };
+        // the next chunk's loads are in flight while the current one is reduced
+        double xn[kQrRows][kQrWc];
+        auto load_chunk = [&](int ch) {
+            const int c0 = chunk_col(ch);
+#pragma unroll
+            for (int s = 0; s < kQrRows; ++s) {
+                const long long r = min(row0 + s * kQrThreads, m - 1);
+#pragma unroll
+                for (int cc = 0; cc < kQrWc; ++cc) xn[s][cc] = A[r + (long long)min(c0 + cc, w - 1) * lda];
+            }
+        };
+        if (nch > 0) load_chunk(0);
         for (int r0 = 0; r0 < nch; r0 += kQrRound) {
             const int rn = min(kQrRound, nch - r0);
             for (int k = 0; k < rn; ++k) {
-                const int ch = r0 + k;
-                const int c0 = ch < nleft ? kQrWc * ch : cb + kQrNB + kQrWc * (ch - nleft);
                 double x[kQrRows][kQrWc];
 #pragma unroll
-                for (int s = 0; s < kQrRows; ++s) {
-                    const long long r = min(row0 + s * kQrThreads, m - 1);
+                for (int s = 0; s < kQrRows; ++s)
 #pragma unroll
-                    for (int cc = 0; cc < kQrWc; ++cc) x[s][cc] = A[r + (long long)min(c0 + cc, w - 1) * lda];
-                }
+                    for (int cc = 0; cc < kQrWc; ++cc) x[s][cc] = xn[s][cc];
+                if (r0 + k + 1 < nch) load_chunk(r0 + k + 1);
                 double acc[kQrWv];
 #pragma unroll
                 for (int cc = 0; cc < kQrWc; ++cc)
@@ -338,8 +348,7 @@ __global__ __launch_bounds__(kQrThreads) void qr_panel_kernel(QrPanelArgs a) {
             __syncthreads();
             for (int e = tid; e < rn * kQrWv; e += kQrThreads) {
                 const int k = e / kQrWv, ev = e % kQrWv;
-                const int ch = r0 + k;
-                const int c = (ch < nleft ? kQrWc * ch : cb + kQrNB + kQrWc * (ch - nleft)) + ev / kQrNB;
+                const int c = chunk_col(r0 + k) + ev / kQrNB;
                 if (c < w)
                     Wp[(ev % kQrNB) + kQrNB * c] = (red[0][k][ev] + red[1][k][ev]) + (red[2][k][ev] + red[3][k][ev]);
             }
@@ -385,25 +394,37 @@ __global__ __launch_bounds__(kQrThreads) void qr_panel_kernel(QrPanelArgs a) {
             }
         }
         __syncthreads();
-        for (int c00 = c1; c00 < w; c00 += 4) {
-            double x[kQrRows][4];
+        {
+            // the update, 4 columns at a time, the next 4 loaded during the current
+            double yn[kQrRows][4];
+            auto load_cols = [&](int c00) {
 #pragma unroll
-            for (int s = 0; s < kQrRows; ++s) {
-                const long long r = min(row0 + s * kQrThreads, m - 1);
+                for (int s = 0; s < kQrRows; ++s) {
+                    const long long r = min(row0 + s * kQrThreads, m - 1);
 #pragma unroll
-                for (int cc = 0; cc < 4; ++cc) x[s][cc] = A[r + (long long)min(c00 + cc, w - 1) * lda];
-            }
+                    for (int cc = 0; cc < 4; ++cc) yn[s][cc] = A[r + (long long)min(c00 + cc, w - 1) * lda];
+                }
+            };
+            if (c1 < w) load_cols(c1);
+            for (int c00 = c1; c00 < w; c00 += 4) {
+                double x[kQrRows][4];
 #pragma unroll
-            for (int cc = 0; cc < 4; ++cc) {
-                const int c = c00 + cc;
-                if (c < w) {
+                for (int s = 0; s < kQrRows; ++s)
 #pragma unroll
-                    for (int s = 0; s < kQrRows; ++s) {
-                        const int i = row0 + s * kQrThreads;
-                        double t = 0.0;
+                    for (int cc = 0; cc < 4; ++cc) x[s][cc] = yn[s][cc];
+                if (c00 + 4 < w) load_cols(c00 + 4);
 #pragma unroll
-                        for (int l = 0; l < kQrNB; ++l) t = t + X[s][l] * Ys[l][c - c1];
-                        if (i >= cb && i < m) A[i + (long long)c * lda] = x[s][cc] - t;
+                for (int cc = 0; cc < 4; ++cc) {
+                    const int c = c00 + cc;
+                    if (c < w) {
+#pragma unroll
+                        for (int s = 0; s < kQrRows; ++s) {
+                            const int i = row0 + s * kQrThreads;
+                            double t = 0.0;
+#pragma unroll
+                            for (int l = 0; l < kQrNB; ++l) t = t + X[s][l] * Ys[l][c - c1];
+                            if (i >= cb && i < m) A[i + (long long)c * lda] = x[s][cc] - t;
+                        }
                     }
                 }
             }
@@ -417,7 +438,7 @@ __global__ __launch_bounds__(kQrThreads) void qr_panel_kernel(QrPanelArgs a) {
             double acc[kQrNB];
 #pragma unroll
             for (int q = 0; q < kQrNB; ++q) acc[q] = 0.0;
-#pragma unroll 4
+#pragma unroll 16
             for (int c = run * kWave; c < cb; ++c) {
                 const double tv = a.T[rr + (long long)c * w];
                 const double t = r <= c ? tv : 0.0;          // T is upper triangular
