@@ -164,6 +164,55 @@ def qr_leg(lu, n, reps):
             "flops": "4n^3/3", "pct_fp64_peak": round(100 * gf / 1e3 / FP64_PEAK_TFLOPS, 2), "runs": reps}
 
 
+def band_leg(lu, n, w, reps):
+    """FP64 two-sided reduction to band form (band_reduce, bandwidth w) of a
+    uniform[-1,1) n x n matrix: median over reps timed runs after one warm-up,
+    HIP events on the reduction's stream; the pristine matrix is restored
+    before each run outside the timed region.  GFLOP/s on the 8n^3/3 count of
+    the full bidiagonal reduction, as the paper reports it."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(13)
+    A0 = lu.colmajor(n)
+    A0.uniform_(-1.0, 1.0, generator=g)
+    A = lu.colmajor(n)
+    tq = torch.zeros(n, dtype=torch.float64, device="cuda")
+    tp = torch.zeros(n, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()             # the input is built on the default stream
+    ts = []
+    for r in range(reps + 1):
+        with torch.cuda.stream(stream):
+            A.copy_(A0)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            rc = lu.band_reduce(A, w, tq, tp, stream=stream)
+            e1.record(stream)
+        stream.synchronize()
+        if rc != 0:
+            raise RuntimeError("band_reduce returned %d" % rc)
+        st, _ = lu.lu_factor_info()
+        if r:
+            ts.append(e0.elapsed_time(e1))
+        print("bench: band run %d %.1f ms status %d" % (r, e0.elapsed_time(e1), st), file=sys.stderr, flush=True)
+        if st != 0:
+            raise RuntimeError("band: status %d" % st)
+    t = statistics.median(ts)
+    gf = 8.0 * n ** 3 / 3.0 / (t * 1e-3) / 1e9
+    # |B[0,0]| is the 2-norm of column 0 of A, and the band keeps ||A||_F
+    r00 = abs(float(A[0, 0]))
+    c0 = float(torch.linalg.vector_norm(A0[:, 0]))
+    if abs(r00 - c0) > 1e-10 * c0:
+        raise RuntimeError("band: |B[0,0]| = %r, column norm %r" % (r00, c0))
+    del A0, A, tq, tp
+    torch.cuda.empty_cache()
+    return {"workload": "FP64 two-sided reduction to upper band form (SVD stage 1) of a uniform[-1,1) "
+                        "%d x %d matrix, bandwidth %d" % (n, n, w),
+            "w": w, "t_reduce_ms": round(t, 3), "gflops": round(gf, 1), "flops": "8n^3/3",
+            "pct_fp64_peak": round(100 * gf / 1e3 / FP64_PEAK_TFLOPS, 2), "runs": reps}
+
+
 def cpu_baseline(budget_s=20.0):
     """Time the CPU oracle on a bounded sample of the same workload: one
     factorization of a smaller uniform[-1,1) matrix, sized by cubic
@@ -199,6 +248,8 @@ def main():
     ap.add_argument("--no-ir", action="store_true")
     ap.add_argument("--no-chol", action="store_true", help="skip the Cholesky measurement")
     ap.add_argument("--no-qr", action="store_true", help="skip the QR measurement")
+    ap.add_argument("--no-band", action="store_true", help="skip the band-reduction measurement")
+    ap.add_argument("--band-w", type=int, default=384, help="bandwidth of the band-reduction leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the hot path is built and measured on a single MI355X); "
@@ -342,6 +393,8 @@ def main():
         out["cholesky"] = cholesky_leg(lu, n, args.steps)
     if not args.no_qr:
         out["qr"] = qr_leg(lu, n, args.steps)
+    if not args.no_band:
+        out["band"] = band_leg(lu, n, args.band_w, args.steps)
     if not args.no_cpu_baseline:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()
