@@ -59,32 +59,35 @@ def gemm_algorithmic_bytes(lu, n, b, depth, taper):
     return tot / max(cnt, 1)
 
 
-def device_spd(lu, n, seed):
-    """SPD workload on the device: the symmetric part (B + B^T)/2 of a
-    uniform[-1,1) matrix B with each diagonal entry set to its row's absolute
-    sum (strictly diagonally dominant)."""
+def device_spd(lu, n, seed, A):
+    """SPD workload on the device, written into the column-major n x n tensor
+    A: the symmetric part (B + B^T)/2 of a uniform[-1,1) matrix B with each
+    diagonal entry set to its row's absolute sum (strictly diagonally
+    dominant).  Temporaries stay at 4096-column blocks."""
     import torch
     g = torch.Generator(device="cuda")
     g.manual_seed(seed)
-    A = lu.colmajor(n)
     A.uniform_(-1.0, 1.0, generator=g)
     for c0 in range(0, n, 4096):
         c1 = min(n, c0 + 4096)
         sym = (A[c0:c1, :].clone() + A[:, c0:c1].t()) / 2.0
         A[c0:c1, :] = sym
         A[:, c0:c1] = sym.t()
-    A.diagonal().copy_(A.abs().sum(dim=1))
+        del sym
+    rowsum = torch.zeros(n, dtype=A.dtype, device=A.device)
+    for c0 in range(0, n, 4096):
+        rowsum += A[:, c0:min(n, c0 + 4096)].abs().sum(dim=1)
+    A.diagonal().copy_(rowsum)
     return A
 
 
-def cholesky_leg(lu, n, reps):
+def cholesky_leg(lu, n, reps, A0, A):
     """FP64 Cholesky with look-ahead (chol_factor, default schedule) on the SPD
     workload: median over reps timed factorizations after one warm-up, HIP
     events on the factorization's stream; the pristine matrix is restored
     before each run outside the timed region."""
     import torch
-    A0 = device_spd(lu, n, 7)
-    A = lu.colmajor(n)
+    device_spd(lu, n, 7, A0)
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()             # the input is built on the default stream
     ts = []
@@ -108,8 +111,6 @@ def cholesky_leg(lu, n, reps):
             raise RuntimeError("cholesky: status %d info %d" % (st, info))
     t = statistics.median(ts)
     gf = n ** 3 / 3.0 / (t * 1e-3) / 1e9
-    del A0, A
-    torch.cuda.empty_cache()
     return {"workload": "FP64 Cholesky with look-ahead of an SPD n=%d matrix (symmetric uniform[-1,1) part, "
                         "diagonal = row absolute sum)" % n,
             "schedule": {"b": 256, "depth": 2, "panel_cus": 32}, "t_factor_ms": round(t, 3),
@@ -117,7 +118,7 @@ def cholesky_leg(lu, n, reps):
             "runs": reps}
 
 
-def qr_leg(lu, n, reps):
+def qr_leg(lu, n, reps, A0, A):
     """FP64 Householder QR with look-ahead (qr_factor, default schedule) of a
     uniform[-1,1) n x n matrix: median over reps timed factorizations after one
     warm-up, HIP events on the factorization's stream; the pristine matrix is
@@ -126,9 +127,7 @@ def qr_leg(lu, n, reps):
     import torch
     g = torch.Generator(device="cuda")
     g.manual_seed(11)
-    A0 = lu.colmajor(n)
     A0.uniform_(-1.0, 1.0, generator=g)
-    A = lu.colmajor(n)
     tau = torch.zeros(n, dtype=torch.float64, device="cuda")
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()             # the input is built on the default stream
@@ -157,14 +156,13 @@ def qr_leg(lu, n, reps):
     c0 = float(torch.linalg.vector_norm(A0[:, 0]))
     if abs(r00 - c0) > 1e-10 * c0:
         raise RuntimeError("qr: |R[0,0]| = %r, column norm %r" % (r00, c0))
-    del A0, A, tau
-    torch.cuda.empty_cache()
+    del tau
     return {"workload": "FP64 Householder QR with look-ahead of a uniform[-1,1) %d x %d matrix" % (n, n),
             "schedule": {"b": 128, "depth": 2}, "t_factor_ms": round(t, 3), "gflops": round(gf, 1),
             "flops": "4n^3/3", "pct_fp64_peak": round(100 * gf / 1e3 / FP64_PEAK_TFLOPS, 2), "runs": reps}
 
 
-def band_leg(lu, n, w, reps):
+def band_leg(lu, n, w, reps, A0, A):
     """FP64 two-sided reduction to band form (band_reduce, bandwidth w) of a
     uniform[-1,1) n x n matrix: median over reps timed runs after one warm-up,
     HIP events on the reduction's stream; the pristine matrix is restored
@@ -173,9 +171,7 @@ def band_leg(lu, n, w, reps):
     import torch
     g = torch.Generator(device="cuda")
     g.manual_seed(13)
-    A0 = lu.colmajor(n)
     A0.uniform_(-1.0, 1.0, generator=g)
-    A = lu.colmajor(n)
     tq = torch.zeros(n, dtype=torch.float64, device="cuda")
     tp = torch.zeros(n, dtype=torch.float64, device="cuda")
     stream = torch.cuda.Stream()
@@ -205,8 +201,7 @@ def band_leg(lu, n, w, reps):
     c0 = float(torch.linalg.vector_norm(A0[:, 0]))
     if abs(r00 - c0) > 1e-10 * c0:
         raise RuntimeError("band: |B[0,0]| = %r, column norm %r" % (r00, c0))
-    del A0, A, tq, tp
-    torch.cuda.empty_cache()
+    del tq, tp
     return {"workload": "FP64 two-sided reduction to upper band form (SVD stage 1) of a uniform[-1,1) "
                         "%d x %d matrix, bandwidth %d" % (n, n, w),
             "w": w, "t_reduce_ms": round(t, 3), "gflops": round(gf, 1), "flops": "8n^3/3",
@@ -390,11 +385,11 @@ def main():
                            "avg_launch_us": round(gemm_ms * 1e3 / gemm_launches, 2),
                            "avg_launch_gflop": round(gemm_flops / gemm_launches / 1e9, 3)}
     if not args.no_chol:
-        out["cholesky"] = cholesky_leg(lu, n, args.steps)
+        out["cholesky"] = cholesky_leg(lu, n, args.steps, A0, A)
     if not args.no_qr:
-        out["qr"] = qr_leg(lu, n, args.steps)
+        out["qr"] = qr_leg(lu, n, args.steps, A0, A)
     if not args.no_band:
-        out["band"] = band_leg(lu, n, args.band_w, args.steps)
+        out["band"] = band_leg(lu, n, args.band_w, args.steps, A0, A)
     if not args.no_cpu_baseline:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

@@ -118,7 +118,11 @@ DeviceState* device_state(int* err) {
         long long v = std::atoll(e);
         if (v > 0) s->spin_limit = v;                    // debug knob: tiny bound forces the timeout path
     }
-    if (hipStreamCreateWithFlags(&s->panel_stream, hipStreamNonBlocking) != hipSuccess ||
+    // the three streams are created together, so the runtime spreads them over
+    // distinct hardware queues whatever streams the caller has made: work on
+    // them can then run concurrently (the caller's stream is joined by events)
+    if (hipStreamCreateWithFlags(&s->update_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&s->panel_stream, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&s->swap_stream, hipStreamNonBlocking) != hipSuccess) {
         *err = LU_ERR_HIP; delete s; return nullptr;
     }
@@ -142,6 +146,7 @@ void release_all() {
         hipSetDevice(s->dev);
         hipDeviceSynchronize();
         for (auto& e : s->events) hipEventDestroy(e);
+        if (s->update_stream) hipStreamDestroy(s->update_stream);
         if (s->panel_stream) hipStreamDestroy(s->panel_stream);
         if (s->swap_stream) hipStreamDestroy(s->swap_stream);
         if (s->sync) hipFree(s->sync);
@@ -296,12 +301,15 @@ int execute(DeviceState* s, int n, T* A, long long lda, int* ipiv, int* info, co
     for (const PlanTask& t : *plan) nrec += t.record ? 1 : 0;
     if ((rc = ensure_events(s, nrec + 2 * kPlanStreams + 2))) return rc;
     const int ring = (int)s->events.size();
-    hipStream_t streams[kPlanStreams] = {stream, s->panel_stream, s->swap_stream};
+    // the left interchanges are ordered on the update stream: run beside the
+    // panel they slow it down more than they gain
+    hipStream_t streams[kPlanStreams] = {s->update_stream, s->panel_stream, s->update_stream};
     // entry join: the library streams start after everything already on `stream`
     hipEvent_t ev0 = s->events[s->ev_next]; s->ev_next = (s->ev_next + 1) % ring;
     LU_HIP(hipEventRecord(ev0, stream));
     LU_HIP(hipStreamWaitEvent(s->panel_stream, ev0, 0));
     LU_HIP(hipStreamWaitEvent(s->swap_stream, ev0, 0));
+    LU_HIP(hipStreamWaitEvent(s->update_stream, ev0, 0));
     std::vector<int> ev_of(plan->size(), -1);
     for (size_t ti = 0; ti < plan->size(); ++ti) {
         const PlanTask& t = (*plan)[ti];
@@ -362,7 +370,7 @@ int execute(DeviceState* s, int n, T* A, long long lda, int* ipiv, int* info, co
         }
     }
     // exit join
-    for (int u = 1; u < kPlanStreams; ++u) {
+    for (int u = 0; u < kPlanStreams; ++u) {
         hipEvent_t ev1 = s->events[s->ev_next]; s->ev_next = (s->ev_next + 1) % ring;
         LU_HIP(hipEventRecord(ev1, streams[u]));
         LU_HIP(hipStreamWaitEvent(stream, ev1, 0));

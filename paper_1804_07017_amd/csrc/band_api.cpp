@@ -12,8 +12,9 @@
 // All products run on the trailing-update GEMM kernel.  Look-ahead (Sec. 4
 // applied to the two-sided reduction): the right-hand update of iteration k
 // writes the next column panel's columns first; that panel is then factored
-// on the panel stream while the rest of the update runs on the caller's
-// stream, and iteration k + 1 joins it before its left-hand update.
+// on the panel stream while the rest of the update runs on the library's
+// update stream, and iteration k + 1 joins it before its left-hand update.
+// The caller's stream is joined by events on entry and exit.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,7 +28,7 @@ namespace lu {
 namespace {
 
 int band_execute(DeviceState* s, int n, double* A, long long lda, int w, double* tauq, double* taup,
-                 hipStream_t st) {
+                 hipStream_t caller) {
     int rc;
     const size_t nw = (size_t)n * w;
     const int ks = s->qr_split_rows;
@@ -81,11 +82,13 @@ int band_execute(DeviceState* s, int n, double* A, long long lda, int w, double*
 
     // look-ahead: the column panel of the next iteration is factored on the
     // panel stream once the right-hand update has written its columns, while
-    // the rest of that update runs on the caller's stream
+    // the rest of that update runs on the update stream
     hipStream_t ps = s->panel_stream;
+    hipStream_t st = s->update_stream;
     hipEvent_t ev0 = next_event();
-    LU_HIP(hipEventRecord(ev0, st));
+    LU_HIP(hipEventRecord(ev0, caller));
     LU_HIP(hipStreamWaitEvent(ps, ev0, 0));
+    LU_HIP(hipStreamWaitEvent(st, ev0, 0));
     if ((rc = panel(A, lda, n, std::min(w, n), tauq, L, st))) return rc;
     hipEvent_t pending = nullptr;              // the column panel factored ahead, not yet joined
     for (int k = 0; k < n; k += w) {
@@ -149,6 +152,9 @@ int band_execute(DeviceState* s, int n, double* A, long long lda, int w, double*
         }
     }
     if (pending) LU_HIP(hipStreamWaitEvent(st, pending, 0));
+    hipEvent_t done = next_event();
+    LU_HIP(hipEventRecord(done, st));
+    LU_HIP(hipStreamWaitEvent(caller, done, 0));
     return 0;
 }
 

@@ -31,11 +31,12 @@ int chol_execute(DeviceState* s, int n, double* A, long long lda, int* info, int
     for (const PlanTask& t : plan) nrec += t.record ? 1 : 0;
     if ((rc = ensure_events(s, nrec + 2 * kPlanStreams + 2))) return rc;
     const int ring = (int)s->events.size();
-    hipStream_t streams[kPlanStreams] = {stream, s->panel_stream, s->swap_stream};
+    hipStream_t streams[kPlanStreams] = {s->update_stream, s->panel_stream, s->swap_stream};
     hipEvent_t ev0 = s->events[s->ev_next]; s->ev_next = (s->ev_next + 1) % ring;
     LU_HIP(hipEventRecord(ev0, stream));
     LU_HIP(hipStreamWaitEvent(s->panel_stream, ev0, 0));
     LU_HIP(hipStreamWaitEvent(s->swap_stream, ev0, 0));
+    LU_HIP(hipStreamWaitEvent(s->update_stream, ev0, 0));
     std::vector<int> ev_of(plan.size(), -1);
     for (size_t ti = 0; ti < plan.size(); ++ti) {
         const PlanTask& t = plan[ti];
@@ -85,7 +86,7 @@ int chol_execute(DeviceState* s, int n, double* A, long long lda, int* info, int
             ev_of[ti] = e;
         }
     }
-    for (int u = 1; u < kPlanStreams; ++u) {
+    for (int u = 0; u < kPlanStreams; ++u) {
         hipEvent_t ev1 = s->events[s->ev_next]; s->ev_next = (s->ev_next + 1) % ring;
         LU_HIP(hipEventRecord(ev1, streams[u]));
         LU_HIP(hipStreamWaitEvent(stream, ev1, 0));

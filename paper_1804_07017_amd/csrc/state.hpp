@@ -30,6 +30,7 @@ struct DeviceState {
     long long spin_limit = 0;          // ~2 s of the device wall clock
     int panel_occupancy = 1;           // panel kernel register budget variant (LU_PANEL_OCC)
     int wide_rows = 20480;             // FP64 panels taller than this use 1024 rows per group (LU_WIDE_ROWS)
+    hipStream_t update_stream = nullptr;  // the bulk trailing update
     hipStream_t panel_stream = nullptr;
     hipStream_t swap_stream = nullptr;   // interchanges of finished columns (off the critical path)
     std::vector<hipEvent_t> events;    // ring used for cross-stream dependencies
