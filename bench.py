@@ -30,7 +30,7 @@ FP64_PEAK_TFLOPS = 78.6
 # counter reads for the bench's own n*n*8-byte device copy (see
 # profiles/gemm_f64_n32768_hbm_traffic.md).  Valid only for the schedule and the
 # GEMM source it was measured with; otherwise the bench reports null.
-GEMM_TRAFFIC = {"n": 32768, "b": 256, "depth": 2, "taper": 1, "gemm_source_sha256_16": "dbc1ca152be45594",
+GEMM_TRAFFIC = {"n": 32768, "b": 256, "depth": 2, "taper": 1, "gemm_source_sha256_16": "d36504d1a6bc4cb6",
                 "bytes_per_launch": 2022112872}
 
 

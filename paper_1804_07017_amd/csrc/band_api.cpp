@@ -108,8 +108,8 @@ int band_execute(DeviceState* s, int n, double* A, long long lda, int w, double*
             if (launch_gemm_split<double>(kw, nc, mk, ks, L.VT, kw, C, (int)lda, Wst, kw, cnt, st)) return LU_ERR_HIP;
             if (slices > 1 && launch_qr_wsum(Wst, slices, cnt, W, st)) return LU_ERR_HIP;
             if (launch_fill_zero(Y, (size_t)cnt * sizeof(double), st)) return LU_ERR_HIP;
-            if (launch_gemm<double>(kw, nc, kw, L.TT, kw, W, kw, Y, kw, st)) return LU_ERR_HIP;
-            if (launch_gemm<double>(mk, nc, kw, L.Vw, mk, Y, kw, C, (int)lda, st)) return LU_ERR_HIP;
+            if (launch_gemm_hh<double>(kw, nc, kw, L.TT, kw, W, kw, Y, kw, st)) return LU_ERR_HIP;
+            if (launch_gemm_hh<double>(mk, nc, kw, L.Vw, mk, Y, kw, C, (int)lda, st)) return LU_ERR_HIP;
         }
         // 2. row panel (as the QR of its transpose) and the right-hand update
         const int c0 = k + w;
@@ -130,10 +130,10 @@ int band_execute(DeviceState* s, int n, double* A, long long lda, int w, double*
             if (launch_gemm_split<double>(md, wp, np, ks, D, (int)lda, R.Vw, np, Wst, md, cnt, st)) return LU_ERR_HIP;
             if (slices > 1 && launch_qr_wsum(Wst, slices, cnt, W, st)) return LU_ERR_HIP;
             if (launch_fill_zero(Y, (size_t)cnt * sizeof(double), st)) return LU_ERR_HIP;
-            if (launch_gemm<double>(md, wp, wp, W, md, R.T, wp, Y, md, st)) return LU_ERR_HIP;       // Y2 = -W2 T
+            if (launch_gemm_hh<double>(md, wp, wp, W, md, R.T, wp, Y, md, st)) return LU_ERR_HIP;       // Y2 = -W2 T
             // D -= Y2 V^T: the next column panel's columns first (the same
             // per-element operations as one product over all columns)
-            if (launch_gemm<double>(md, kn, wp, Y, md, R.VT, wp, D, (int)lda, st)) return LU_ERR_HIP;
+            if (launch_gemm_hh<double>(md, kn, wp, Y, md, R.VT, wp, D, (int)lda, st)) return LU_ERR_HIP;
         }
         // the next column panel ahead, on the panel stream
         {
@@ -147,7 +147,7 @@ int band_execute(DeviceState* s, int n, double* A, long long lda, int w, double*
         }
         if (md > 0 && np > kn) {
             double* D = A + (k + wp) + (long long)c0 * lda;
-            if (launch_gemm<double>(md, np - kn, wp, Y, md, R.VT + (size_t)kn * wp, wp, D + (long long)kn * lda,
+            if (launch_gemm_hh<double>(md, np - kn, wp, Y, md, R.VT + (size_t)kn * wp, wp, D + (long long)kn * lda,
                                     (int)lda, st)) return LU_ERR_HIP;
         }
     }

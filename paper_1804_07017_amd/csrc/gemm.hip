@@ -219,6 +219,15 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_nn_sub(int M, int N, int K, 
     gemm_tile<T, BK, false, false>(M, N, K, A, lda, B, ldb, C, ldc, 0);
 }
 
+// The same product for the Householder block updates (QR, band reduction):
+// a kernel of its own so that profiles keep the LU's trailing update apart.
+template <typename T, int BK>
+__global__ __launch_bounds__(kThreads, 2) void gemm_nn_hh(int M, int N, int K, const T* __restrict__ A,
+                                                           int lda, const T* __restrict__ B, int ldb,
+                                                           T* __restrict__ C, int ldc) {
+    gemm_tile<T, BK, false, false>(M, N, K, A, lda, B, ldb, C, ldc, 0);
+}
+
 // Split-K form for products with a long k range and few output tiles (the
 // V^T C product of a Householder block update): the work-groups of slice
 // z = blockIdx.y take k in [z*ks, min(K, (z+1)*ks)) and store
@@ -415,6 +424,17 @@ int launch_gemm(int M, int N, int K, const T* A, int lda, const T* B, int ldb, T
 }
 
 template <typename T>
+int launch_gemm_hh(int M, int N, int K, const T* A, int lda, const T* B, int ldb, T* C, int ldc,
+                   hipStream_t stream) {
+    if (M <= 0 || N <= 0 || K <= 0) return 0;
+    const long long tiles = (long long)((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
+    if (tiles > 0x7fffffffLL) return -1;
+    hipLaunchKernelGGL((gemm_nn_hh<T, 16>), dim3((unsigned)tiles), dim3(kThreads), 0, stream, M, N, K, A, lda, B,
+                       ldb, C, ldc);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+template <typename T>
 int launch_gemm_split(int M, int N, int K, int ks, const T* A, int lda, const T* B, int ldb, T* C, int ldc,
                       long long cstride, hipStream_t stream) {
     if (M <= 0 || N <= 0 || K <= 0) return 0;
@@ -451,6 +471,8 @@ int launch_gemm_half(int M, int N, int K, const H* Ah, int lda_h, const H* Bh, i
 template int launch_gemm<double>(int, int, int, const double*, int, const double*, int, double*, int,
                                  hipStream_t);
 template int launch_gemm<float>(int, int, int, const float*, int, const float*, int, float*, int, hipStream_t);
+template int launch_gemm_hh<double>(int, int, int, const double*, int, const double*, int, double*, int,
+                                    hipStream_t);
 template int launch_gemm_split<double>(int, int, int, int, const double*, int, const double*, int, double*, int,
                                        long long, hipStream_t);
 template int launch_syrk_lower<double>(int, int, int, const double*, int, const double*, int, double*, int, int,

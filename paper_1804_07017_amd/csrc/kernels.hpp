@@ -75,6 +75,9 @@ int launch_cols_half(const float* B, long long ldb, int k, int n, H* Uh, long lo
 
 template <typename T>
 int launch_gemm(int M, int N, int K, const T* A, int lda, const T* B, int ldb, T* C, int ldc, hipStream_t stream);
+// C -= A B for the Householder block updates (the trailing-update tile, its own kernel name)
+template <typename T>
+int launch_gemm_hh(int M, int N, int K, const T* A, int lda, const T* B, int ldb, T* C, int ldc, hipStream_t stream);
 // slices z of ks k-values: C + z*cstride = -A[:, slice] B[slice, :] (not accumulated)
 template <typename T>
 int launch_gemm_split(int M, int N, int K, int ks, const T* A, int lda, const T* B, int ldb, T* C, int ldc,

@@ -112,8 +112,8 @@ int qr_execute(DeviceState* s, int m, int n, double* A, long long lda, double* t
             if (launch_gemm_split<double>(wk, nc, mk, ks, VTk, wk, C, (int)lda, Wst, wk, cnt, st)) return LU_ERR_HIP;
             if (slices > 1 && launch_qr_wsum(Wst, slices, cnt, W, st)) return LU_ERR_HIP;
             if (launch_fill_zero(Ym, (size_t)cnt * sizeof(double), st)) return LU_ERR_HIP;
-            if (launch_gemm<double>(wk, nc, wk, TTk, wk, W, wk, Ym, wk, st)) return LU_ERR_HIP;
-            if (launch_gemm<double>(mk, nc, wk, Vk, mk, Ym, wk, C, (int)lda, st)) return LU_ERR_HIP;  // C -= V Ym
+            if (launch_gemm_hh<double>(wk, nc, wk, TTk, wk, W, wk, Ym, wk, st)) return LU_ERR_HIP;
+            if (launch_gemm_hh<double>(mk, nc, wk, Vk, mk, Ym, wk, C, (int)lda, st)) return LU_ERR_HIP;  // C -= V Ym
         } else {
             return LU_ERR_UNSUPPORTED;
         }
