@@ -24,16 +24,18 @@
  * Memory and ownership: A, tauq and taup are DEVICE pointers owned by the
  * caller (tauq, taup: n doubles each); lda >= max(1, n).  The library keeps
  * workspace (the transposed row panel, explicit V and V^T, T, the products'
- * buffers: about (6 + ceil(n / 2048)) n w doubles) cached per device;
+ * buffers: about (7 + ceil(n / 2048)) n w doubles) cached per device;
  * lu_release frees it.
  *
  * Errors: 0 = enqueued; -1 n < 0, -2 A NULL, -3 lda < max(1, n), -4 w < 1 or
  * w > 384, -5 tauq NULL, -6 taup NULL; LU_ERR_UNSUPPORTED for n > 65536 (the
- * panel kernel holds at most 1024 rows per compute unit on at most 64 units);
+ * panel kernel holds at most 1024 rows per work-group on at most 64 compute units);
  * LU_ERR_* (lu.h) for HIP failures, workspace and panel-barrier time-outs
  * (lu_factor_info reports the latter).
  *
- * Async: enqueues on `stream` (every step in order on it) and returns without
+ * Async: ordered on `stream` (the reduction runs on the library's update
+ * stream, the column panels factored ahead on its panel stream, both ordered
+ * after `stream` on entry and joined back into it on exit) and returns without
  * a host synchronization.  Not thread-safe per device.
  */
 #ifndef LU_MI355X_BAND_H

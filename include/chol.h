@@ -25,9 +25,10 @@
  * when given, else to the library's INFO word, read with lu_factor_info()
  * (lu.h), which synchronizes with the last factorization of either kind.
  *
- * Async: both calls enqueue on `stream` (the library's panel stream is
- * ordered after it on entry and joined back on exit) and return without a
- * host synchronization.  Not thread-safe per device.
+ * Async: both calls are ordered on `stream` (the factorization runs on the
+ * library's update and panel streams, ordered after `stream` on entry and
+ * joined back into it on exit) and return without a host synchronization.
+ * Not thread-safe per device.
  */
 #ifndef LU_MI355X_CHOL_H
 #define LU_MI355X_CHOL_H

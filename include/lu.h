@@ -31,9 +31,13 @@
  *   - A singular U is not an error: the factorization completes and info
  *     reports the first exactly-zero pivot (1-based column), as LAPACK does.
  *   - Calls are asynchronous on `stream` unless stated otherwise, and are not
- *     thread-safe: one host thread per device at a time.
- *   - The library owns its workspace (device buffers, an internal panel
- *     stream, events), cached per device until lu_release().
+ *     thread-safe: one host thread per device at a time.  The factorizations
+ *     run on the library's own update and panel streams (created together so
+ *     that they use different hardware queues), ordered after `stream` on
+ *     entry; `stream` waits for them on exit (events), so work enqueued on it
+ *     afterwards sees the result.
+ *   - The library owns its workspace (device buffers, its streams, events),
+ *     cached per device until lu_release().
  */
 #ifndef LU_MI355X_H
 #define LU_MI355X_H

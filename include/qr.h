@@ -19,11 +19,13 @@
  * Errors: 0 = enqueued; -1 m < 0, -2 n < 0 or n > m, -3 A NULL, -4 lda,
  * -5 tau NULL, -6 invalid schedule (b not in {32,64,128,256}, depth not in
  * {0,1,2}, panel_cus > 256); LU_ERR_UNSUPPORTED for m > 65536 (the panel
- * kernel holds at most 1024 rows per compute unit on at most 64 units);
+ * kernel holds at most 1024 rows per work-group on at most 64 compute units);
  * LU_ERR_* (lu.h) for HIP failures, workspace and panel-barrier time-outs
  * (lu_factor_info reports the latter).
  *
- * Async: enqueues on `stream` and returns without a host synchronization.
+ * Async: ordered on `stream` (the factorization runs on the library's update
+ * and panel streams, ordered after `stream` on entry and joined back into it
+ * on exit) and returns without a host synchronization.
  * Not thread-safe per device.
  */
 #ifndef LU_MI355X_QR_H

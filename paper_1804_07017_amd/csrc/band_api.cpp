@@ -71,8 +71,8 @@ int band_execute(DeviceState* s, int n, double* A, long long lda, int w, double*
         pa.sync_next = s->sync + 2 * (1 - s->sync_slot);
         s->sync_slot = 1 - s->sync_slot;
         pa.spin_limit = s->spin_limit;
-        const int wgs = (m + 1023) / 1024;
-        if (wgs > 64 || wgs > s->num_cus) return LU_ERR_UNSUPPORTED;
+        const int wgs = (m + kQrPanelGroupRows - 1) / kQrPanelGroupRows;
+        if (wgs > kQrPanelMaxGroups || wgs > s->num_cus) return LU_ERR_UNSUPPORTED;
         // T's strictly lower part stays zero: the right-hand update multiplies by T itself
         if (launch_fill_zero(o.T, (size_t)pw * pw * sizeof(double), q)) return LU_ERR_HIP;
         if (launch_qr_panel(pa, wgs, q)) return LU_ERR_HIP;
@@ -171,7 +171,7 @@ int band_reduce_impl(int n, double* A, int lda, int w, double* tauq, double* tau
     int err;
     DeviceState* s = device_state(&err);
     if (!s) return err;
-    if ((long long)n > 1024LL * std::min(64, s->num_cus)) return LU_ERR_UNSUPPORTED;
+    if ((long long)n > (long long)kQrPanelGroupRows * std::min(kQrPanelMaxGroups, s->num_cus)) return LU_ERR_UNSUPPORTED;
     if (launch_fill_zero(s->info, sizeof(int), stream)) return LU_ERR_HIP;
     if (launch_fill_zero(taup, (size_t)n * sizeof(double), stream)) return LU_ERR_HIP;
     s->last_stream = stream;

@@ -124,7 +124,10 @@ struct QrPanelArgs {
 };
 // workspace of the QR panel: per-group partial sums and the block-phase W
 constexpr int kQrMaxPanelW = 384;
-constexpr int kQrPartWords = 128 + 64 * 16 + 64 * 16 * kQrMaxPanelW + 16 * kQrMaxPanelW;
+constexpr int kQrPanelGroupRows = 1024;  // panel rows per work-group (the launch has ceil(m / 1024) groups)
+constexpr int kQrPanelMaxGroups = 64;
+constexpr int kQrPartWords = 2 * kQrPanelMaxGroups + kQrPanelMaxGroups * 16 + kQrPanelMaxGroups * 16 * kQrMaxPanelW +
+                             16 * kQrMaxPanelW;
 int launch_qr_panel(const QrPanelArgs& args, int wgs, hipStream_t stream);
 // Vw (m x w, ld m) and VT (w x m, ld w): the panel's unit-lower V, explicit;
 // TT = T^T (w x w, ld w)

@@ -40,7 +40,7 @@ namespace lu {
 namespace {
 
 constexpr int kQrThreads = 256;
-constexpr int kQrRows = 4;          // panel rows per thread
+constexpr int kQrRows = kQrPanelGroupRows / 256;   // panel rows per thread
 constexpr int kQrGroupRows = kQrThreads * kQrRows;
 constexpr int kQrMaxW = kQrMaxPanelW;   // the widest panel: QR block size, band width
 constexpr int kQrNB = 16;           // columns of an inner block (held in registers)
@@ -49,11 +49,12 @@ constexpr int kQrWc = 2;                         // columns per chunk of the blo
 constexpr int kQrWv = kQrWc * kQrNB;             // values per lane per chunk
 constexpr int kQrRound = 512 / kQrWv;            // chunks per LDS round
 // partial-sum workspace (doubles)
-constexpr int kPartSs = 0;                                   // [64] sums of squares
-constexpr int kPartAlpha = 64;                               // the diagonal entry of column J
-constexpr int kPartDot = 128;                                // [64][16] in-block dot products
-constexpr int kPartW = kPartDot + 64 * kQrNB;                // [64][16 * w] partial W
-constexpr int kPartWs = kPartW + 64 * kQrNB * kQrMaxW;       // [16 * w] summed W
+constexpr int kQrMaxGroups = kQrPanelMaxGroups;
+constexpr int kPartSs = 0;                                            // [groups] sums of squares
+constexpr int kPartAlpha = kQrMaxGroups;                              // the diagonal entry of column J
+constexpr int kPartDot = 2 * kQrMaxGroups;                            // [groups][16] in-block dot products
+constexpr int kPartW = kPartDot + kQrMaxGroups * kQrNB;               // [groups][16 * w] partial W
+constexpr int kPartWs = kPartW + kQrMaxGroups * kQrNB * kQrMaxW;      // [16 * w] summed W
 static_assert(kPartWs + kQrNB * kQrMaxW == kQrPartWords, "QR workspace layout");
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -92,8 +93,8 @@ struct QrShared {
     double Ys[kQrNB][kQrMaxW];              // T_b^T W of the columns right of the block
     double Us[kQrMaxW][kQrNB];              // (V^T V_b) T_b of the columns left of it
     double sc[4];                           // tau, scal, beta
-    double pss[65];                         // the groups' sums of squares, [64] the diagonal entry
-    double pdot[64 * kQrNB];                // the groups' dot products
+    double pss[kQrMaxGroups + 1];           // the groups' sums of squares, then the diagonal entry
+    double pdot[kQrMaxGroups * kQrNB];      // the groups' dot products
 };
 
 // Where a thread is: its group, lanes and first row.
@@ -153,12 +154,12 @@ __device__ __forceinline__ bool qr_column(double (&X)[kQrRows][kQrNB], QrShared&
     // 2. the reflector, identical in every group (the partials loaded in
     //    parallel, summed in group order)
     if (tid < P) sh.pss[tid] = ld_dev(&part[kPartSs + tid]);
-    if (tid == kQrThreads - 1) sh.pss[64] = ld_dev(&part[kPartAlpha]);
+    if (tid == kQrThreads - 1) sh.pss[kQrMaxGroups] = ld_dev(&part[kPartAlpha]);
     __syncthreads();
     if (tid == 0) {
         double sig = 0.0;
         for (int q = 0; q < P; ++q) sig = sig + sh.pss[q];
-        const double alpha = sh.pss[64];
+        const double alpha = sh.pss[kQrMaxGroups];
         double tau = 0.0, scal = 1.0, beta = alpha;
         if (sig != 0.0) {
             const double nrm = sqrt(alpha * alpha + sig);
@@ -492,7 +493,7 @@ inline int grid_for(long long work) {
 }  // namespace
 
 int launch_qr_panel(const QrPanelArgs& args, int wgs, hipStream_t stream) {
-    if (args.w < 1 || args.w > kQrMaxW || args.m < args.w || wgs < 1 || wgs > 64) return -1;
+    if (args.w < 1 || args.w > kQrMaxW || args.m < args.w || wgs < 1 || wgs > kQrMaxGroups) return -1;
     if (wgs != (args.m + kQrThreads * kQrRows - 1) / (kQrThreads * kQrRows)) return -1;
     hipLaunchKernelGGL(qr_panel_kernel, dim3(wgs), dim3(kQrThreads), 0, stream, args);
     return hipGetLastError() == hipSuccess ? 0 : -2;

@@ -96,8 +96,8 @@ int qr_execute(DeviceState* s, int m, int n, double* A, long long lda, double* t
             pa.spin_limit = s->spin_limit;
             // one group per 1024 rows (4 per thread), fixed by the panel height so
             // that the reduction order does not depend on the schedule
-            const int wgs = (mk + 1023) / 1024;
-            if (wgs > 64 || wgs > s->num_cus) return LU_ERR_UNSUPPORTED;
+            const int wgs = (mk + kQrPanelGroupRows - 1) / kQrPanelGroupRows;
+            if (wgs > kQrPanelMaxGroups || wgs > s->num_cus) return LU_ERR_UNSUPPORTED;
             if (launch_qr_panel(pa, wgs, st)) return LU_ERR_HIP;
             if (launch_qr_prep(pa.A, lda, mk, wk, Tk, Vk, VTk, TTk, st)) return LU_ERR_HIP;
         } else if (t.kind == kTaskUpdate) {
@@ -151,7 +151,7 @@ int qr_factor_impl(int m, int n, double* A, int lda, double* tau, const lu_sched
     int err;
     DeviceState* s = device_state(&err);
     if (!s) return err;
-    if ((long long)m > 1024LL * std::min(64, s->num_cus)) return LU_ERR_UNSUPPORTED;
+    if ((long long)m > (long long)kQrPanelGroupRows * std::min(kQrPanelMaxGroups, s->num_cus)) return LU_ERR_UNSUPPORTED;
     // lu_factor_info reports on this factorization: no INFO of its own (0),
     // panel-barrier time-outs through the barrier error words
     if (launch_fill_zero(s->info, sizeof(int), stream)) return LU_ERR_HIP;

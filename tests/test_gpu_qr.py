@@ -35,6 +35,17 @@ def test_qr_matches_oracle(gpu, m, n, b, depth, cus, lda):
     assert np.abs(tau - otau).max() <= 1e-11
 
 
+@pytest.mark.parametrize("m,n,b,depth", [(9000, 200, 128, 2), (20000, 300, 64, 1)])
+def test_qr_tall_skinny_matches_oracle(gpu, m, n, b, depth):
+    """Panels of 9 and 20 work-groups: the cross-group sums against the oracle."""
+    A = synth.rhs(m, seed=m + n, nrhs=n)
+    F, tau = _qr(gpu, A, b, depth, 32)
+    oF, otau = oracle.geqrf(A, nthreads=8)
+    scale = max(1.0, np.abs(np.triu(oF)).max())
+    assert np.abs(F - oF).max() <= 1e-11 * scale
+    assert np.abs(tau - otau).max() <= 1e-11
+
+
 def test_qr_schedule_invariance_bitwise(gpu):
     A = synth.uniform(2600, seed=31)
     ref = None
