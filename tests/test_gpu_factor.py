@@ -182,7 +182,7 @@ def test_solve_matches_oracle(gpu, n, nrhs):
     assert np.abs(X - Xo).max() <= 1e-8 * np.abs(Xo).max()
 
 
-def test_solve_north_star_form(gpu):
+def test_solve_square_default_stream_form(gpu):
     import torch
     n = 333
     A = synth.uniform(n, seed=2)

@@ -96,7 +96,7 @@ def test_ir_rejects_nonfinite_input(gpu):
 
 
 @pytest.mark.timeout(600)
-def test_north_star_mixed_fp16_ir_n32768(gpu):
+def test_mixed_fp16_ir_n32768(gpu):
     """C4(a) at full size: FP16 trailing GEMM, FP32 panel/TRSM, FP64 refinement.
     The residual is recomputed independently with torch's FP64 matrix-vector
     product; the oracle's solution is out of reach at this size."""
