@@ -9,7 +9,8 @@
 // Panel kernel: one persistent launch of P = ceil(m / 1024) work-groups (256
 // threads each), group g owning the 1024-row block starting at g*1024 and
 // thread t its rows g*1024 + t + s*256 (s < 4).  The panel is processed in
-// inner blocks of 16 columns that each thread holds in registers for its rows.
+// inner blocks of 16 columns that each thread holds in registers for its rows,
+// as a ring of 16 slots with the current column in slot 0.
 // Per column J of an inner block, with two device-wide barriers (without
 // cache maintenance: the few words exchanged use device-scope atomics):
 //   1. each group's partial sum of squares below the diagonal (the owner of

@@ -1,10 +1,13 @@
 // Householder QR with look-ahead: the LU's task list without interchanges
-// (plan.cpp with lswap = false) on the same three streams.  PANEL(k): the QR
-// panel kernel, then the explicit V and V^T of the panel (ring of four
-// slots: every update of panel k has finished before panel k + 4 starts, for
-// any look-ahead depth up to 2).  UPDATE(k, c0, c1) on rows kb..m of columns
-// [c0, c1): W = -V^T C, Ym = -T^T W, C -= V Ym (= C - V T^T V^T C), the two
-// products on the trailing-update GEMM kernel.
+// (plan.cpp with lswap = false) on the library's update and panel streams.
+// PANEL(k): the QR panel kernel, then the explicit V, V^T and T^T of the panel
+// (ring of four slots: every update of panel k has finished before panel
+// k + 4 starts, for any look-ahead depth up to 2).  UPDATE(k, c0, c1) on rows
+// kb..m of columns [c0, c1): W = -V^T C as a split-K product over fixed
+// 2048-row slices summed in slice order (the slices do not depend on the
+// column range, so the look-ahead leaves every element's arithmetic
+// unchanged), Ym = -T^T W, C -= V Ym (= C - V T^T V^T C), the products on the
+// trailing-update tile.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
