@@ -229,6 +229,40 @@ def cpu_baseline(budget_s=20.0):
             "sample": "one FP64 partial-pivoting LU of a uniform[-1,1) %dx%d matrix (%.1f s)" % (n, n, t)}
 
 
+def oracle_rate(kind, budget_s=8.0):
+    """GFLOP/s of the CPU oracle of one of the other workloads on a bounded
+    sample (one run sized by cubic extrapolation to take about budget_s):
+    'chol' potrf of the SPD matrix (n^3/3), 'qr' geqrf of a uniform matrix
+    (4n^3/3), 'band' the band reduction (8n^3/3, w = 384; single-threaded)."""
+    import oracle
+    import synth
+    cores = min(16, len(os.sched_getaffinity(0)))
+    flops = {"chol": 1.0 / 3.0, "qr": 4.0 / 3.0, "band": 8.0 / 3.0}[kind]
+    n, t = 512, 0.0
+    for _ in range(5):
+        if kind == "chol":
+            A = synth.spd(n, seed=7)
+            t0 = time.perf_counter()
+            oracle.potrf(A, nthreads=cores)
+        elif kind == "qr":
+            A = synth.uniform(n, seed=11)
+            t0 = time.perf_counter()
+            oracle.geqrf(A, nthreads=cores)
+        else:
+            A = synth.uniform(n, seed=13)
+            t0 = time.perf_counter()
+            oracle.gebrd_band(A, min(384, n))
+        t = time.perf_counter() - t0
+        if t >= 0.4 * budget_s or n >= 16384:
+            break
+        n = min(16384, max(n + 256, int(n * (budget_s / max(t, 1e-3)) ** (1 / 3)))) // 256 * 256
+    used = 1 if kind == "band" else cores
+    what = {"chol": "Cholesky of the SPD", "qr": "Householder QR of a uniform[-1,1)",
+            "band": "band reduction (w = %d) of a uniform[-1,1)" % min(384, n)}[kind]
+    return {"value": round(flops * n ** 3 / t / 1e9, 3), "unit": "GFLOP/s", "cores": used, "kind": "oracle",
+            "sample": "one FP64 %s %dx%d matrix (%.1f s)" % (what, n, n, t)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -393,6 +427,10 @@ def main():
     if not args.no_cpu_baseline:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()
+        for key, kind in (("cholesky", "chol"), ("qr", "qr"), ("band", "band")):
+            if key in out:
+                print("bench: cpu oracle (%s)" % kind, file=sys.stderr, flush=True)
+                out[key]["cpu_oracle"] = oracle_rate(kind)
     print(json.dumps(out))
 
 
