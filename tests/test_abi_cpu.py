@@ -57,6 +57,28 @@ def test_argument_errors_before_any_device_call():
     assert lib.lu_solve_ir(0, 1, None, 1, None, 1, None, 1, 2, 5, ctypes.byref(it), ctypes.byref(res), None) == 0
     assert lib.lu_k_panel(0, 4, 8, 8, 4, 8, 0, None, None) == -3
     assert lib.lu_k_gemm(0, 4, 4, 4, 8, 2, 8, 4, 8, 4, None) == -6
+    # Cholesky, QR and the band reduction check their arguments the same way
+    assert lib.chol_factor(-1, None, 1, None) == -1
+    assert lib.chol_factor(4, None, 4, None) == -2
+    assert lib.chol_factor(4, 8, 3, None) == -3
+    assert lib.chol_factor(0, None, 1, None) == 0
+    assert lib.chol_factor_ex(4, 8, 4, ctypes.byref(lu.Schedule(100, 1, 16)), None, None) == -4
+    assert lib.qr_factor(-1, 1, 8, 1, 8, None) == -1
+    assert lib.qr_factor(3, 4, 8, 4, 8, None) == -2
+    assert lib.qr_factor(4, 4, None, 4, 8, None) == -3
+    assert lib.qr_factor(4, 4, 8, 3, 8, None) == -4
+    assert lib.qr_factor(4, 4, 8, 4, None, None) == -5
+    assert lib.qr_factor(0, 0, None, 1, None, None) == 0
+    assert lib.qr_factor_ex(4, 4, 8, 4, 8, ctypes.byref(lu.Schedule(100, 1, 16)), None) == -6
+    assert lib.qr_factor_ex(4, 4, 8, 4, 8, ctypes.byref(lu.Schedule(128, 3, 16)), None) == -6
+    assert lib.band_reduce(-1, 8, 1, 2, 8, 8, None) == -1
+    assert lib.band_reduce(4, None, 4, 2, 8, 8, None) == -2
+    assert lib.band_reduce(4, 8, 3, 2, 8, 8, None) == -3
+    assert lib.band_reduce(4, 8, 4, 0, 8, 8, None) == -4
+    assert lib.band_reduce(4, 8, 4, 385, 8, 8, None) == -4
+    assert lib.band_reduce(4, 8, 4, 2, None, 8, None) == -5
+    assert lib.band_reduce(4, 8, 4, 2, 8, None, None) == -6
+    assert lib.band_reduce(0, None, 1, 2, None, None, None) == 0
 
 
 def test_selector_file_errors(tmp_path):
