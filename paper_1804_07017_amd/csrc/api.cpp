@@ -155,7 +155,7 @@ void release_all() {
                           &s->partial, &s->ir_r, &s->ir_x32, &s->ir_a32, &s->ir_a64, &s->ir_norms, &s->ir_ipiv,
                           &s->ir_b, &s->qr_v, &s->qr_vt, &s->qr_t, &s->qr_tt, &s->qr_w, &s->qr_ws, &s->qr_ym, &s->qr_part,
                           &s->band_z, &s->band_v, &s->band_vt, &s->band_t, &s->band_tt, &s->band_w,
-                          &s->band_y, &s->band_ws};
+                          &s->band_y, &s->band_ws, &s->band_pan};
         for (Buffer* b : bufs) release(*b);
         delete s;
     }

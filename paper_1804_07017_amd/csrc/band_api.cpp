@@ -27,6 +27,8 @@ namespace lu {
 
 namespace {
 
+constexpr int kBandSub = 128;   // sub-panel width of wide band panels
+
 int band_execute(DeviceState* s, int n, double* A, long long lda, int w, double* tauq, double* taup,
                  hipStream_t caller) {
     int rc;
@@ -46,6 +48,22 @@ int band_execute(DeviceState* s, int n, double* A, long long lda, int w, double*
     if (max_slices > 1 && (rc = ensure(s->band_ws, (size_t)max_slices * nw * sizeof(double)))) return rc;
     if ((rc = ensure(s->qr_part, (size_t)kQrPartWords * sizeof(double)))) return rc;
     if ((rc = ensure_events(s, 2 * (size_t)((n + w - 1) / w) + 4))) return rc;
+    // wide panels: sub-panel workspace (T, T^T, V of the current sub-panel, V^T
+    // of every sub-panel, the Gram and U blocks, the in-panel update's W, Y and
+    // k-slices), used only by the stream that factors the panel
+    const int nsub = (w + kBandSub - 1) / kBandSub;
+    const size_t sub2 = (size_t)kBandSub * kBandSub, nsw = (size_t)n * kBandSub, wsw = (size_t)w * kBandSub;
+    const size_t pan_words = 2 * sub2 + nsw + (size_t)nsub * nsw + 4 * wsw + (size_t)std::max(1, max_slices) * wsw;
+    if (w > kBandSub && (rc = ensure(s->band_pan, pan_words * sizeof(double)))) return rc;
+    double* Tsub = w > kBandSub ? reinterpret_cast<double*>(s->band_pan.ptr) : nullptr;
+    double* TTsub = Tsub + sub2;
+    double* Vsub = TTsub + sub2;
+    double* VTs = Vsub + nsw;                  // [nsub][kBandSub x n], ld kBandSub
+    double* Gn = VTs + (size_t)nsub * nsw;     // -(V_i^T V_j) blocks, kBandSub x kBandSub, ld kBandSub
+    double* Ub = Gn + wsw;                     // U_i = G_i T_j blocks
+    double* Wpn = Ub + wsw;                    // in-panel update W, Y
+    double* Ypn = Wpn + wsw;
+    double* WSpn = Ypn + wsw;                  // k-slices of the panel's own products
     struct Ops { double *Vw, *VT, *T, *TT; };
     Ops L{reinterpret_cast<double*>(s->band_v.ptr), reinterpret_cast<double*>(s->band_vt.ptr),
           reinterpret_cast<double*>(s->band_t.ptr), reinterpret_cast<double*>(s->band_tt.ptr)};
@@ -80,6 +98,76 @@ int band_execute(DeviceState* s, int n, double* A, long long lda, int w, double*
         return 0;
     };
 
+    // a panel wider than kBandSub: sub-panels of kBandSub columns, each factored
+    // by the panel kernel and applied to the panel's columns right of it as a
+    // block reflector; T is assembled blockwise, T[0:j0, j] = -T[0:j0, 0:j0]
+    // (V[:, 0:j0]^T V_j) T_j, so the panel's (V, T) is that of the single-launch
+    // panel up to rounding, at the cost of three narrow panels instead of one
+    // wide one (the panel kernel's blocked work grows with the square of the width)
+    auto panel_wide = [&](double* P, long long ld, int m, int pw, double* tau, const Ops& o, hipStream_t q) -> int {
+        if (pw <= kBandSub) return panel(P, ld, m, pw, tau, o, q);
+        if (launch_fill_zero(o.T, (size_t)pw * pw * sizeof(double), q)) return LU_ERR_HIP;
+        for (int j0 = 0, i = 0; j0 < pw; j0 += kBandSub, ++i) {
+            const int jw = std::min(kBandSub, pw - j0);
+            const int mj = m - j0;
+            double* Pj = P + j0 + (long long)j0 * ld;
+            double* VTi = VTs + (size_t)i * nsw;
+            // the sub-panel: reflectors and T_j, explicit V_j, V_j^T, T_j^T
+            QrPanelArgs pa;
+            pa.A = Pj;
+            pa.lda = ld;
+            pa.m = mj;
+            pa.w = jw;
+            pa.tau = tau + j0;
+            pa.T = Tsub;
+            pa.part = reinterpret_cast<double*>(s->qr_part.ptr);
+            pa.sync = s->sync + 2 * s->sync_slot;
+            pa.sync_next = s->sync + 2 * (1 - s->sync_slot);
+            s->sync_slot = 1 - s->sync_slot;
+            pa.spin_limit = s->spin_limit;
+            const int wgs = (mj + kQrPanelGroupRows - 1) / kQrPanelGroupRows;
+            if (wgs > kQrPanelMaxGroups || wgs > s->num_cus) return LU_ERR_UNSUPPORTED;
+            if (launch_fill_zero(Tsub, (size_t)jw * jw * sizeof(double), q)) return LU_ERR_HIP;
+            if (launch_qr_panel(pa, wgs, q)) return LU_ERR_HIP;
+            if (launch_qr_prep(Pj, ld, mj, jw, Tsub, Vsub, VTi, TTsub, q)) return LU_ERR_HIP;
+            if (launch_copy_f64(Tsub, jw, o.T + j0 + (long long)j0 * pw, pw, jw, jw, q)) return LU_ERR_HIP;
+            const int slices = (mj + ks - 1) / ks;
+            // T's block above T_j, one earlier sub-panel (rows of T) at a time
+            for (int ip = 0; ip < i; ++ip) {
+                const int off = j0 - ip * kBandSub;    // rows of sub-panel ip's V^T before row j0
+                const double* VTp = VTs + (size_t)ip * nsw + (size_t)off * kBandSub;
+                const long long cnt = (long long)kBandSub * jw;
+                double* Gi = Gn + (size_t)ip * kBandSub * jw;
+                double* Wst = slices > 1 ? WSpn : Gi;
+                if (launch_gemm_split<double>(kBandSub, jw, mj, ks, VTp, kBandSub, Vsub, mj, Wst, kBandSub, cnt, q))
+                    return LU_ERR_HIP;                                            // -V_ip^T V_j
+                if (slices > 1 && launch_qr_wsum(Wst, slices, cnt, Gi, q)) return LU_ERR_HIP;
+                double* Ui = Ub + (size_t)ip * kBandSub * jw;
+                if (launch_fill_zero(Ui, (size_t)cnt * sizeof(double), q)) return LU_ERR_HIP;
+                if (launch_gemm_hh<double>(kBandSub, jw, jw, Gi, kBandSub, Tsub, jw, Ui, kBandSub, q))
+                    return LU_ERR_HIP;                                            // U = G T_j
+            }
+            for (int ip = 0; ip < i; ++ip)                                        // T[0:j0, j] -= T[0:j0, ip] U_ip
+                if (launch_gemm_hh<double>(j0, jw, kBandSub, o.T + (long long)ip * kBandSub * pw, pw,
+                                           Ub + (size_t)ip * kBandSub * jw, kBandSub, o.T + (long long)j0 * pw, pw,
+                                           q)) return LU_ERR_HIP;
+            // the panel's columns right of the sub-panel: C -= V_j (T_j^T (V_j^T C))
+            const int ncp = pw - j0 - jw;
+            if (ncp > 0) {
+                double* C = Pj + (long long)jw * ld;
+                const long long cnt = (long long)jw * ncp;
+                double* Wst = slices > 1 ? WSpn : Wpn;
+                if (launch_gemm_split<double>(jw, ncp, mj, ks, VTi, jw, C, (int)ld, Wst, jw, cnt, q)) return LU_ERR_HIP;
+                if (slices > 1 && launch_qr_wsum(Wst, slices, cnt, Wpn, q)) return LU_ERR_HIP;
+                if (launch_fill_zero(Ypn, (size_t)cnt * sizeof(double), q)) return LU_ERR_HIP;
+                if (launch_gemm_hh<double>(jw, ncp, jw, TTsub, jw, Wpn, jw, Ypn, jw, q)) return LU_ERR_HIP;
+                if (launch_gemm_hh<double>(mj, ncp, jw, Vsub, mj, Ypn, jw, C, (int)ld, q)) return LU_ERR_HIP;
+            }
+        }
+        if (launch_qr_prep(P, ld, m, pw, o.T, o.Vw, o.VT, o.TT, q)) return LU_ERR_HIP;
+        return 0;
+    };
+
     // look-ahead: the column panel of the next iteration is factored on the
     // panel stream once the right-hand update has written its columns, while
     // the rest of that update runs on the update stream
@@ -89,7 +177,7 @@ int band_execute(DeviceState* s, int n, double* A, long long lda, int w, double*
     LU_HIP(hipEventRecord(ev0, caller));
     LU_HIP(hipStreamWaitEvent(ps, ev0, 0));
     LU_HIP(hipStreamWaitEvent(st, ev0, 0));
-    if ((rc = panel(A, lda, n, std::min(w, n), tauq, L, st))) return rc;
+    if ((rc = panel_wide(A, lda, n, std::min(w, n), tauq, L, st))) return rc;
     hipEvent_t pending = nullptr;              // the column panel factored ahead, not yet joined
     for (int k = 0; k < n; k += w) {
         const int kw = std::min(w, n - k);
@@ -118,7 +206,7 @@ int band_execute(DeviceState* s, int n, double* A, long long lda, int w, double*
         const int wp = std::min(kw, np);
         double* Rp = A + k + (long long)c0 * lda;
         if (launch_transpose_f64(Rp, lda, wp, np, Z, np, st)) return LU_ERR_HIP;
-        if ((rc = panel(Z, np, np, wp, taup + k, R, st))) return rc;
+        if ((rc = panel_wide(Z, np, np, wp, taup + k, R, st))) return rc;
         if (launch_transpose_f64(Z, np, np, wp, Rp, lda, st)) return LU_ERR_HIP;
         const int md = n - k - wp;
         const int kn = std::min(w, n - c0);    // width of the next column panel (its columns start at c0)
@@ -141,7 +229,7 @@ int band_execute(DeviceState* s, int n, double* A, long long lda, int w, double*
             LU_HIP(hipEventRecord(ready, st));
             LU_HIP(hipStreamWaitEvent(ps, ready, 0));
             const int k1 = k + w;
-            if ((rc = panel(A + k1 + (long long)k1 * lda, lda, n - k1, kn, tauq + k1, L, ps))) return rc;
+            if ((rc = panel_wide(A + k1 + (long long)k1 * lda, lda, n - k1, kn, tauq + k1, L, ps))) return rc;
             pending = next_event();
             LU_HIP(hipEventRecord(pending, ps));
         }

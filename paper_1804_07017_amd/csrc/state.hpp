@@ -51,7 +51,7 @@ struct DeviceState {
     Buffer lh, uh, rs, cs;
     // QR: explicit V / V^T / T of the last four panels, W and -T^T W per update stream, panel partial sums
     Buffer qr_v, qr_vt, qr_t, qr_tt, qr_w, qr_ws, qr_ym, qr_part;
-    Buffer band_z, band_v, band_vt, band_t, band_tt, band_w, band_y, band_ws;
+    Buffer band_z, band_v, band_vt, band_t, band_tt, band_w, band_y, band_ws, band_pan;
     int qr_split_rows = 2048;         // k-slice height of the QR V^T C product (env QR_SPLIT_ROWS)
     // solves / refinement
     Buffer solve_moves, flags, partial, ir_r, ir_x32, ir_a32, ir_a64, ir_norms, ir_ipiv, ir_b;
