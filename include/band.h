@@ -24,7 +24,8 @@
  * Memory and ownership: A, tauq and taup are DEVICE pointers owned by the
  * caller (tauq, taup: n doubles each); lda >= max(1, n).  The library keeps
  * workspace (the transposed row panel, explicit V and V^T, T, the products'
- * buffers: about (7 + ceil(n / 2048)) n w doubles) cached per device;
+ * buffers: about (7 + ceil(n / 2048)) n w doubles, plus (1 + ceil(w / 128)) n 128
+ * doubles for the sub-panels of a panel wider than 128) cached per device;
  * lu_release frees it.
  *
  * Errors: 0 = enqueued; -1 n < 0, -2 A NULL, -3 lda < max(1, n), -4 w < 1 or
