@@ -256,7 +256,7 @@ def _device_residual(gpu, dA0, dLU, ipiv):
 
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("b,depth,cus,taper", [(256, 1, 16, -1), (512, 2, 8, -1), (256, 2, 32, 1)])
-def test_c3_32768_uniform(gpu, b, depth, cus, taper):
+def test_uniform_32768_schedules(gpu, b, depth, cus, taper):
     """Full-size FP64 look-ahead LU: scaled residual with a library GEMM, the
     pivots are a legal permutation, every multiplier is bounded by 1, and the
     first panel's pivots equal the oracle's (a plain column search over A)."""
@@ -280,7 +280,7 @@ def test_c3_32768_uniform(gpu, b, depth, cus, taper):
 
 
 @pytest.mark.timeout(900)
-def test_c3_32768_planted_factors(gpu):
+def test_planted_factors_32768(gpu):
     """A = P L U with L scaled to a = 0.1 sqrt(1024/n) (||L^-1|| as at n=1024):
     the pivots and both factors are recovered."""
     import torch
