@@ -28,7 +28,7 @@ def _factor(gpu, A_np, b, depth, panel_cus=16, prec=0, lda=None, taper=-1):
     return gpu.to_host(dA).astype(np.float64), ipiv.cpu().numpy()[:n], int(info.item())
 
 
-def test_c1_512_b64_depth0_matches_oracle(gpu):
+def test_512_b64_depth0_matches_oracle(gpu):
     A = synth.uniform(512, seed=1)
     LU, ipiv, info = _factor(gpu, A, 64, 0)
     oLU, oip, oinfo = oracle.getrf(A, nthreads=8)
@@ -207,7 +207,7 @@ def test_fp32_factor_residual(gpu):
     assert r <= 16.0
 
 
-def test_c2_8192_lookahead_and_solve(gpu):
+def test_8192_lookahead_and_solve(gpu):
     import torch
     n = 8192
     A = synth.uniform(n, seed=1)
