@@ -8,9 +8,11 @@ One step = the whole hot path on one batch of synthetic input resident in HBM:
   3. lu_solve_ir in mixed precision (FP16 trailing GEMM, FP32 panel/TRSM, FP64
      refinement) on the row-dominant matrix of the same size.
 `value` is the FP64 factorization rate 2/3 n^3 / t_factor (median over the
-timed steps, HIP events on the stream the factorization runs on).
+timed steps, HIP events on the stream the factorization runs on).  After the
+timed steps: the Cholesky, QR and band-reduction legs (each timed the same
+way), then the CPU oracles on bounded samples.
 
-Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  --gpus N with N > 1 exits: the path runs on one GPU.
 """
 import argparse
 import json
