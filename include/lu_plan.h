@@ -74,6 +74,12 @@ int lu_plan_panels(int n, int b, int taper, int prec, int* starts, int max_start
 int lu_plan_build_panels(int n, const int* starts, int npanels, int depth, lu_plan_task_t* out,
                          int max_tasks);
 
+/* As lu_plan_build_panels; interchanges = 0 gives the task list of the
+ * factorizations without row interchanges (Cholesky, QR: no LU_TASK_LSWAP
+ * tasks and no waits on pivots), interchanges != 0 the LU's.  Same returns. */
+int lu_plan_build_panels_ex(int n, const int* starts, int npanels, int depth, int interchanges,
+                            lu_plan_task_t* out, int max_tasks);
+
 #ifdef __cplusplus
 }
 #endif

@@ -66,6 +66,7 @@ _SIGS = {
     "band_reduce": (_I, [_I, _P, _I, _I, _P, _P, _P]),
     "lu_plan_panels": (_I, [_I, _I, _I, _I, ctypes.POINTER(_I), _I]),
     "lu_plan_build_panels": (_I, [_I, ctypes.POINTER(_I), _I, _I, ctypes.POINTER(PlanTask), _I]),
+    "lu_plan_build_panels_ex": (_I, [_I, ctypes.POINTER(_I), _I, _I, _I, ctypes.POINTER(PlanTask), _I]),
     "lu_k_panel": (_I, [_I, _I, _I, _P, _I, _P, _I, _P, _P]),
     "lu_k_update": (_I, [_I, _I, _I, _I, _P, _I, _P, _P, _I, _P]),
     "lu_k_gemm": (_I, [_I, _I, _I, _I, _P, _I, _P, _I, _P, _I, _P]),
@@ -337,6 +338,20 @@ def lu_plan_build_panels(n, starts, depth, max_tasks=None):
     st = (ctypes.c_int * max(1, len(starts)))(*starts)
     arr = (PlanTask * max(1, max_tasks))()
     rc = load().lu_plan_build_panels(int(n), st, N, int(depth), arr, int(max_tasks))
+    if rc < 0:
+        return rc, []
+    return rc, _tasks(arr, rc)
+
+
+def lu_plan_build_panels_ex(n, starts, depth, interchanges, max_tasks=None):
+    """Task list for explicit panel boundaries, with or without the LU's
+    interchange tasks (host only). Returns (rc, list of dicts)."""
+    N = max(0, len(starts) - 1)
+    if max_tasks is None:
+        max_tasks = 8 * N + 16
+    st = (ctypes.c_int * max(1, len(starts)))(*starts)
+    arr = (PlanTask * max(1, max_tasks))()
+    rc = load().lu_plan_build_panels_ex(int(n), st, N, int(depth), int(interchanges), arr, int(max_tasks))
     if rc < 0:
         return rc, []
     return rc, _tasks(arr, rc)

@@ -201,6 +201,18 @@ extern "C" int lu_plan_panels(int n, int b, int taper, int prec, int* starts, in
     return N;
 }
 
+extern "C" int lu_plan_build_panels_ex(int n, const int* starts, int npanels, int depth, int interchanges,
+                                       lu_plan_task_t* out, int max_tasks) {
+    if (n < 0) return -1;
+    if (n > 0 && (!starts || npanels < 1)) return -4;
+    std::vector<int> st;
+    if (n > 0) st.assign(starts, starts + npanels + 1);
+    std::vector<lu::PlanTask> v;
+    int r = lu::build_plan(n, st, depth, v, interchanges != 0);
+    if (r < 0) return r;
+    return export_plan(v, out, max_tasks);
+}
+
 extern "C" int lu_plan_build_panels(int n, const int* starts, int npanels, int depth, lu_plan_task_t* out,
                                     int max_tasks) {
     if (n < 0) return -1;

@@ -7,7 +7,9 @@ import re
 import numpy as np
 import pytest
 
+import oracle
 import paper_1804_07017_amd as lu
+import synth
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -285,3 +287,57 @@ def test_plan_executes_to_the_oracle_result_in_any_legal_order(n, starts, depth)
     LU, ip, info = oracle.getrf(A0)
     assert np.array_equal(results[0][1], ip)
     assert np.abs(results[0][0] - LU).max() <= 1e-10 * max(1.0, np.abs(LU).max())
+
+
+def _run_qr_task(A, tau, t, starts):
+    """One task of the interchange-free plan as the QR executor runs it:
+    PANEL(k) Householder QR of rows kb.. of the panel's columns; UPDATE(k, c0,
+    c1) the panel's block reflector applied to those rows of columns c0..c1."""
+    k = t["step"]
+    kb, w = starts[k], starts[k + 1] - starts[k]
+    if t["kind"] == lu.LU_TASK_PANEL:
+        P = A[kb:, kb:kb + w]
+        for j in range(w):
+            alpha = P[j, j]
+            s = float(np.dot(P[j + 1:, j], P[j + 1:, j]))
+            if s == 0.0:
+                continue
+            beta = -np.sqrt(alpha * alpha + s) if alpha >= 0.0 else np.sqrt(alpha * alpha + s)
+            tau[kb + j] = (beta - alpha) / beta
+            P[j + 1:, j] *= 1.0 / (alpha - beta)
+            P[j, j] = beta
+            v = np.concatenate(([1.0], P[j + 1:, j]))
+            P[j:, j + 1:] -= tau[kb + j] * np.outer(v, v @ P[j:, j + 1:])
+    else:
+        assert t["kind"] == lu.LU_TASK_UPDATE
+        c0, c1 = t["col_begin"], t["col_end"]
+        V = np.tril(A[kb:, kb:kb + w], -1)
+        V[np.arange(w), np.arange(w)] = 1.0
+        for j in range(w):                       # H_0 ... H_{w-1} applied in order: Q^T C
+            v = V[:, j]
+            C = A[kb:, c0:c1]
+            C -= tau[kb + j] * np.outer(v, v @ C)
+
+
+@pytest.mark.parametrize("starts,depth", [([0, 8, 16, 24, 30], 1), ([0, 8, 16, 24, 30], 2),
+                                          ([0, 4, 12, 13, 20], 2), ([0, 10, 20], 0)])
+def test_interchange_free_plan_executes_to_the_qr_oracle(starts, depth):
+    """The task list the QR and Cholesky executors use: no LSWAP tasks, and
+    executed in random legal orders (stream order kept) it gives the QR
+    oracle's factorization."""
+    n = starts[-1]
+    rc, tasks = lu.lu_plan_build_panels_ex(n, starts, depth, 0)
+    assert rc == len(tasks) > 0
+    assert not any(t["kind"] == lu.LU_TASK_LSWAP for t in tasks)
+    rc1, tasks1 = lu.lu_plan_build_panels_ex(n, starts, depth, 1)
+    assert (rc1, tasks1) == lu.lu_plan_build_panels(n, starts, depth)
+    A0 = synth.uniform(n, seed=n + depth)
+    oF, otau = oracle.geqrf(A0)
+    rng = np.random.default_rng(depth + 7)
+    for _ in range(3):
+        A = np.array(A0, order="F", copy=True)
+        tau = np.zeros(n)
+        for i in _random_legal_order(tasks, rng):
+            _run_qr_task(A, tau, tasks[i], starts)
+        assert np.abs(A - oF).max() <= 1e-12
+        assert np.abs(tau - otau).max() <= 1e-13
