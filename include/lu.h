@@ -76,9 +76,14 @@ typedef struct {
 #define LU_ERR_NOMEM       (-102)  /* workspace allocation failed                         */
 #define LU_ERR_UNSUPPORTED (-103)  /* size or option outside what the library supports  */
 #define LU_ERR_NONFINITE   (-104)  /* NaN/Inf met where a finite value is required        */
+#define LU_ERR_SINGULAR    (-105)  /* lu_solve_ir: the FP64 factor has an exactly-zero pivot */
 
-#define LU_IR_OK        0  /* refinement met the FP64 HPL residual test                   */
-#define LU_IR_FELL_BACK 1  /* refinement stalled; the FP64 factorization was used instead */
+#define LU_IR_OK         0  /* the solution meets the FP64 HPL residual test (<= 16)        */
+#define LU_IR_FELL_BACK  1  /* refinement stalled or the working-precision factor was
+                               singular; the FP64 factorization was used and its solution
+                               meets the test                                             */
+#define LU_IR_RESID_HIGH 2  /* the FP64 solution (LU_FP64, or after the fall-back) fails
+                               the HPL test; X holds it                                   */
 
 /* ---- factorization ----------------------------------------------------- */
 
@@ -131,13 +136,19 @@ int lu_solve_ex(int n, int nrhs, const double* LU, int lda, const int* ipiv,
  * repeats until every column meets the HPL test
  *     ||A x - b||_inf / (eps (||A||_inf ||x||_inf + ||b||_inf) n) <= 16,
  *     eps = 2^-53,
- * or max_iter iterations pass.  Without convergence the matrix is refactored
- * in FP64 and LU_IR_FELL_BACK is returned.  Synchronises the stream (the
- * convergence test is read on the host each iteration).
+ * or max_iter iterations pass.  Without convergence (or when the working-
+ * precision factor has a zero pivot) the matrix is refactored in FP64 and
+ * solved plainly.  Synchronises the stream (the convergence test is read on
+ * the host each iteration).  The INFO word and the panel barriers of every
+ * factorization it runs are checked.
  * iters_out / resid_out (host, may be NULL) receive the refinement steps taken
- * and the final worst-column HPL residual.  Returns LU_IR_OK, LU_IR_FELL_BACK,
- * LU_ERR_NONFINITE (NaN/Inf in A or B), or an error: -1 n, -2 nrhs, -3 A,
- * -4 lda, -5 B, -6 ldb, -7 X, -8 ldx, -9 prec, -10 max_iter < 1. */
+ * and the final worst-column HPL residual (NaN when no FP64 solution exists).
+ * Returns LU_IR_OK, LU_IR_FELL_BACK, LU_IR_RESID_HIGH (the FP64 solution
+ * fails the test), LU_ERR_SINGULAR (the FP64 factor has a zero pivot; X is
+ * not written), LU_ERR_NONFINITE (NaN/Inf in A or B, or in the residual),
+ * LU_ERR_BARRIER (a panel barrier timed out), or an argument error: -1 n,
+ * -2 nrhs, -3 A, -4 lda, -5 B, -6 ldb, -7 X, -8 ldx, -9 prec,
+ * -10 max_iter < 1. */
 int lu_solve_ir(int n, int nrhs, const double* A, int lda, const double* B, int ldb,
                 double* X, int ldx, lu_precision_t prec, int max_iter,
                 int* iters_out, double* resid_out, hipStream_t stream);

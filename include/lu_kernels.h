@@ -55,6 +55,26 @@ int lu_k_laswp(lu_precision_t prec, int m, int w, int ncols, const int* ipiv_rel
 int lu_k_timing(int enable);
 int lu_k_timing_read(double* ms, double* flops, int* launches);
 
+/* Host only (no device call): the moves a trailing kernel takes from a
+ * composed interchange list (host int[2 + 4*512]: [0] top count, [1] extra
+ * count, top (dst, src) pairs from [2], extra pairs from [2 + 2*512]; rows
+ * relative to the panel's first row) of a panel of width w (1..512) in a
+ * block of m >= w rows.  The kernels read the list with the same functions:
+ * counts clamped to w, a top move kept only if dst in [0, w) and src in
+ * [0, m), an extra move only if dst in [w, m) and src in [0, w).  Writes the
+ * kept (dst, src) pairs to out (host int[4*512]), top moves first, and
+ * returns (kept top << 16) | kept extra.  Errors: -1 moves, -2 w, -3 m,
+ * -4 out. */
+int lu_k_moves_check(const int* moves, int w, int m, int* out);
+
+/* Host only (no device call): the status lu_solve_ir returns once its FP64
+ * solution is settled -- fp64_info is the INFO of the FP64 factorization
+ * (0 or the first zero pivot, 1-based), fell_back is 1 when refinement in the
+ * working precision was given up, resid the worst-column HPL residual:
+ *   fp64_info != 0 -> LU_ERR_SINGULAR;  resid NaN -> LU_ERR_NONFINITE;
+ *   resid > 16 -> LU_IR_RESID_HIGH;  else LU_IR_FELL_BACK or LU_IR_OK. */
+int lu_ir_outcome(int fp64_info, int fell_back, double resid);
+
 /* Diagnostic: run one v_mfma_f64_16x16x4f64 on lane-indexed inputs
  * (a = lane, b = 100 + lane, c = 0) and write the 64x4 outputs to out (device
  * double[256], lane-major). */

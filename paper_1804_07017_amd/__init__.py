@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(HERE, "liblu_mi355x.so")
 
 LU_FP64, LU_FP32, LU_MIXED_FP16, LU_MIXED_BF16 = 0, 1, 2, 3
 LU_ERR_HIP, LU_ERR_BARRIER, LU_ERR_NOMEM, LU_ERR_UNSUPPORTED, LU_ERR_NONFINITE = -100, -101, -102, -103, -104
-LU_IR_OK, LU_IR_FELL_BACK = 0, 1
+LU_ERR_SINGULAR = -105
+LU_IR_OK, LU_IR_FELL_BACK, LU_IR_RESID_HIGH = 0, 1, 2
 LU_TASK_PANEL, LU_TASK_UPDATE, LU_TASK_LSWAP = 0, 1, 2
 SELECTOR_PARAMS = 490
 
@@ -72,6 +73,8 @@ _SIGS = {
     "lu_k_gemm": (_I, [_I, _I, _I, _I, _P, _I, _P, _I, _P, _I, _P]),
     "lu_k_laswp": (_I, [_I, _I, _I, _I, _P, _P, _I, _P]),
     "lu_k_probe_mfma_f64": (_I, [_P, _P]),
+    "lu_ir_outcome": (_I, [_I, _I, ctypes.c_double]),
+    "lu_k_moves_check": (_I, [_P, _I, _I, _P]),
     "lu_k_timing": (_I, [_I]),
     "lu_k_timing_read": (_I, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(_I)]),

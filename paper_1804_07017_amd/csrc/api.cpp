@@ -19,6 +19,7 @@
 #include "../../include/lu.h"
 #include "../../include/lu_kernels.h"
 #include "kernels.hpp"
+#include "moves.hpp"
 #include "plan.hpp"
 #include "selector.hpp"
 #include "state.hpp"
@@ -138,6 +139,31 @@ DeviceState* device_state(int* err) {
     if (hipMemset(s->cand.ptr, 0, s->cand.bytes) != hipSuccess) { *err = LU_ERR_HIP; return nullptr; }
     g_states[dev] = s;
     return s;
+}
+
+int begin_factorization(DeviceState* s, hipStream_t stream) {
+    const int ring = (int)s->events.size();
+    if (ring < 4) return LU_ERR_HIP;
+    auto next = [&]() {
+        hipEvent_t e = s->events[s->ev_next];
+        s->ev_next = (s->ev_next + 1) % ring;
+        return e;
+    };
+    hipEvent_t ev0 = next(), evp = next(), evs = next(), evc = next();
+    LU_HIP(hipEventRecord(ev0, stream));
+    LU_HIP(hipEventRecord(evp, s->panel_stream));
+    LU_HIP(hipEventRecord(evs, s->swap_stream));
+    LU_HIP(hipStreamWaitEvent(s->update_stream, ev0, 0));
+    LU_HIP(hipStreamWaitEvent(s->update_stream, evp, 0));
+    LU_HIP(hipStreamWaitEvent(s->update_stream, evs, 0));
+    // error words of both barrier slots (sync[1], sync[3]); the counters are
+    // reset by the launches themselves
+    if (launch_fill_zero(s->sync + 1, sizeof(unsigned), s->update_stream)) return LU_ERR_HIP;
+    if (launch_fill_zero(s->sync + 3, sizeof(unsigned), s->update_stream)) return LU_ERR_HIP;
+    LU_HIP(hipEventRecord(evc, s->update_stream));
+    LU_HIP(hipStreamWaitEvent(s->panel_stream, evc, 0));
+    LU_HIP(hipStreamWaitEvent(s->swap_stream, evc, 0));
+    return 0;
 }
 
 void release_all() {
@@ -305,11 +331,10 @@ int execute(DeviceState* s, int n, T* A, long long lda, int* ipiv, int* info, co
     // panel they slow it down more than they gain
     hipStream_t streams[kPlanStreams] = {s->update_stream, s->panel_stream, s->update_stream};
     // entry join: the library streams start after everything already on `stream`
-    hipEvent_t ev0 = s->events[s->ev_next]; s->ev_next = (s->ev_next + 1) % ring;
-    LU_HIP(hipEventRecord(ev0, stream));
-    LU_HIP(hipStreamWaitEvent(s->panel_stream, ev0, 0));
-    LU_HIP(hipStreamWaitEvent(s->swap_stream, ev0, 0));
-    LU_HIP(hipStreamWaitEvent(s->update_stream, ev0, 0));
+    // and after every earlier task of their own; the panel barriers' error
+    // words are cleared in between, so a time-out of an earlier factorization
+    // does not make this one's panels give up at their first wait
+    if ((rc = begin_factorization(s, stream))) return rc;
     std::vector<int> ev_of(plan->size(), -1);
     for (size_t ti = 0; ti < plan->size(); ++ti) {
         const PlanTask& t = (*plan)[ti];
@@ -334,7 +359,7 @@ int execute(DeviceState* s, int n, T* A, long long lda, int* ipiv, int* info, co
             }
         } else if (t.kind == kTaskUpdate) {
             SwapTrsmArgs<T, H> sa;
-            sa.A = A; sa.lda = lda; sa.r0 = kb; sa.w = wk; sa.moves = mv;
+            sa.A = A; sa.lda = lda; sa.r0 = kb; sa.w = wk; sa.moves = mv; sa.m = n - kb;
             sa.c0 = t.col_begin; sa.c1 = t.col_end; sa.linv = linv + (size_t)k * kLinvPer;
             sa.uh = mixed ? Uh + kb : nullptr;
             sa.lduh = lduh;
@@ -360,7 +385,7 @@ int execute(DeviceState* s, int n, T* A, long long lda, int* ipiv, int* info, co
                 }
             }
         } else {
-            if (launch_lswap<T>(A, lda, kb, mv, t.col_begin, t.col_end, st)) return LU_ERR_HIP;
+            if (launch_lswap<T>(A, lda, kb, wk, n - kb, mv, t.col_begin, t.col_end, st)) return LU_ERR_HIP;
         }
         if (t.record) {
             const int e = s->ev_next;
@@ -524,7 +549,7 @@ int lu_k_update(lu_precision_t prec, int m, int w, int ncols, const void* L, int
         double* A = const_cast<double*>(reinterpret_cast<const double*>(L));
         double* linv = reinterpret_cast<double*>(s->linv.ptr);
         if (lu::launch_diag_inv<double>(A, ldl, 0, w, linv, stream)) return LU_ERR_HIP;
-        lu::SwapTrsmArgs<double, _Float16> sa{A, ldl, 0, w, mv, c0, c0 + ncols, linv, nullptr, 0, nullptr};
+        lu::SwapTrsmArgs<double, _Float16> sa{A, ldl, 0, w, mv, m, c0, c0 + ncols, linv, nullptr, 0, nullptr};
         if (lu::launch_swap_trsm<double, _Float16>(sa, stream)) return LU_ERR_HIP;
         if (m > w && lu::launch_gemm<double>(m - w, ncols, w, A + w, ldl, A + (long long)c0 * ldl, ldl,
                                              A + w + (long long)c0 * ldl, ldl, stream))
@@ -533,7 +558,7 @@ int lu_k_update(lu_precision_t prec, int m, int w, int ncols, const void* L, int
         float* A = const_cast<float*>(reinterpret_cast<const float*>(L));
         float* linv = reinterpret_cast<float*>(s->linv.ptr);
         if (lu::launch_diag_inv<float>(A, ldl, 0, w, linv, stream)) return LU_ERR_HIP;
-        lu::SwapTrsmArgs<float, _Float16> sa{A, ldl, 0, w, mv, c0, c0 + ncols, linv, nullptr, 0, nullptr};
+        lu::SwapTrsmArgs<float, _Float16> sa{A, ldl, 0, w, mv, m, c0, c0 + ncols, linv, nullptr, 0, nullptr};
         if (lu::launch_swap_trsm<float, _Float16>(sa, stream)) return LU_ERR_HIP;
         if (m > w && lu::launch_gemm<float>(m - w, ncols, w, A + w, ldl, A + (long long)c0 * ldl, ldl,
                                             A + w + (long long)c0 * ldl, ldl, stream))
@@ -608,8 +633,9 @@ int lu_k_laswp(lu_precision_t prec, int m, int w, int ncols, const int* ipiv_rel
     if (rc) return rc;
     int* mv = reinterpret_cast<int*>(s->solve_moves.ptr);
     if (lu::launch_moves(ipiv_rel, w, m, mv, stream)) return LU_ERR_HIP;
-    if (prec == LU_FP64) return lu::launch_lswap<double>((double*)C, ldc, 0, mv, 0, ncols, stream) ? LU_ERR_HIP : 0;
-    return lu::launch_lswap<float>((float*)C, ldc, 0, mv, 0, ncols, stream) ? LU_ERR_HIP : 0;
+    if (prec == LU_FP64)
+        return lu::launch_lswap<double>((double*)C, ldc, 0, w, m, mv, 0, ncols, stream) ? LU_ERR_HIP : 0;
+    return lu::launch_lswap<float>((float*)C, ldc, 0, w, m, mv, 0, ncols, stream) ? LU_ERR_HIP : 0;
 }
 
 int lu_k_timing(int enable) {
@@ -635,6 +661,25 @@ int lu_k_timing_read(double* ms, double* flops, int* launches) {
     *flops = f;
     *launches = (int)lu::g_timing.used;
     return 0;
+}
+
+int lu_k_moves_check(const int* moves, int w, int m, int* out) {
+    if (!moves) return -1;
+    if (w < 1 || w > lu::kMovesMaxW) return -2;
+    if (m < w) return -3;
+    if (!out) return -4;
+    int k = 0;
+    const int nt = lu::moves_top_count(moves, w), ne = lu::moves_extra_count(moves, w);
+    for (int s = 0; s < nt; ++s) {
+        int d, r;
+        if (lu::moves_top(moves, s, w, m, d, r)) { out[2 * k] = d; out[2 * k + 1] = r; ++k; }
+    }
+    const int ktop = k;
+    for (int s = 0; s < ne; ++s) {
+        int d, r;
+        if (lu::moves_extra(moves, s, w, m, d, r)) { out[2 * k] = d; out[2 * k + 1] = r; ++k; }
+    }
+    return (ktop << 16) | (k - ktop);
 }
 
 int lu_k_probe_mfma_f64(double* out, hipStream_t stream) {

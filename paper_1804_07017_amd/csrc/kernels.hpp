@@ -48,6 +48,7 @@ struct SwapTrsmArgs {
     int r0;               // first row (and column) of the panel of this step
     int w;                // panel width
     const int* moves;     // composed interchanges of the panel (rows relative to r0)
+    int m;                // matrix rows from r0 on (every move row lies in [0, m))
     int c0, c1;           // columns to process
     const T* linv;        // inverses of L11's 16x16 diagonal blocks (launch_diag_inv)
     H* uh;                // optional half copy of U12: uh[col*lduh + t], t = row - r0
@@ -61,8 +62,9 @@ int launch_swap_trsm(const SwapTrsmArgs<T, H>& args, hipStream_t stream);
 // blk of the w x w block at (r0, r0): element (j, k).  ceil(w/16) blocks.
 template <typename T>
 int launch_diag_inv(const T* A, long long lda, int r0, int w, T* linv, hipStream_t stream);
+// rows r0 .. r0+m-1 of columns [c0, c1): the interchanges of a panel of width w
 template <typename T>
-int launch_lswap(T* A, long long lda, int r0, const int* moves, int c0, int c1, hipStream_t stream);
+int launch_lswap(T* A, long long lda, int r0, int w, int m, const int* moves, int c0, int c1, hipStream_t stream);
 int launch_moves(const int* ipiv_rel, int w, int m, int* moves, hipStream_t stream);
 int launch_chunk_moves(const int* ipiv, int n, int W, int* moves, hipStream_t stream);
 template <typename H>

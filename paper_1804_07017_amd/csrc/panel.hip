@@ -296,6 +296,12 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
     if (g == 0 && tid == 0 && a.sync_next) {
         a.sync_next[0] = 0u;   // counter of the next launch's slot (its previous user has finished)
     }
+    if (g == 0 && tid == 0 && a.moves) {
+        // an empty interchange list until the composition at the end: a panel
+        // that gives up at a barrier time-out leaves no stale moves behind
+        a.moves[0] = 0;
+        a.moves[1] = 0;
+    }
 
     auto row_of = [&](int q) { return g * R + q * kPanelThreads + tid; };
     // finished column t (< NB) of the current block, own row q

@@ -60,11 +60,7 @@ int qr_execute(DeviceState* s, int m, int n, double* A, long long lda, double* t
     if ((rc = ensure_events(s, nrec + 2 * kPlanStreams + 2))) return rc;
     const int ring = (int)s->events.size();
     hipStream_t streams[kPlanStreams] = {s->update_stream, s->panel_stream, s->swap_stream};
-    hipEvent_t ev0 = s->events[s->ev_next]; s->ev_next = (s->ev_next + 1) % ring;
-    LU_HIP(hipEventRecord(ev0, stream));
-    LU_HIP(hipStreamWaitEvent(s->panel_stream, ev0, 0));
-    LU_HIP(hipStreamWaitEvent(s->swap_stream, ev0, 0));
-    LU_HIP(hipStreamWaitEvent(s->update_stream, ev0, 0));
+    if ((rc = begin_factorization(s, stream))) return rc;
     std::vector<int> ev_of(plan.size(), -1);
     for (size_t ti = 0; ti < plan.size(); ++ti) {
         const PlanTask& t = plan[ti];

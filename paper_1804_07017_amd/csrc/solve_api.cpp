@@ -9,6 +9,7 @@
 #include <cstring>
 
 #include "../../include/lu.h"
+#include "../../include/lu_kernels.h"
 #include "kernels.hpp"
 #include "state.hpp"
 
@@ -85,9 +86,31 @@ int dev_amax(DeviceState* s, const double* v, int n, hipStream_t stream, double*
     return 0;
 }
 
-// FP64 factor of a copy of A and a plain solve; used for LU_FP64 and as the fallback.
+// Outcome of a factorization enqueued on `stream` with the library's INFO
+// word: waits for it, returns LU_ERR_BARRIER if one of its panel barriers
+// timed out (the error words are cleared for the next call), else 0 with
+// LAPACK INFO in *info.
+int factor_status(DeviceState* s, hipStream_t stream, int* info) {
+    int h = 0;
+    unsigned e[4] = {0, 0, 0, 0};
+    LU_HIP(hipMemcpyAsync(&h, s->info, sizeof(int), hipMemcpyDeviceToHost, stream));
+    LU_HIP(hipMemcpyAsync(e, s->sync, 4 * sizeof(unsigned), hipMemcpyDeviceToHost, stream));
+    LU_HIP(hipStreamSynchronize(stream));
+    *info = h;
+    if (e[1] || e[3]) {
+        if (launch_fill_zero(s->sync + 1, sizeof(unsigned), stream)) return LU_ERR_HIP;
+        if (launch_fill_zero(s->sync + 3, sizeof(unsigned), stream)) return LU_ERR_HIP;
+        LU_HIP(hipStreamSynchronize(stream));
+        return LU_ERR_BARRIER;
+    }
+    return 0;
+}
+
+// FP64 factor of a copy of A and a plain solve; used for LU_FP64 and as the
+// fallback.  A singular FP64 factor (INFO > 0) is reported in *info and
+// leaves X unsolved.
 int fp64_path(DeviceState* s, int n, int nrhs, const double* A, long long lda, const double* B, long long ldb,
-              double* X, long long ldx, hipStream_t stream) {
+              double* X, long long ldx, hipStream_t stream, int* info) {
     int rc;
     if ((rc = ensure(s->ir_a64, (size_t)n * n * sizeof(double)))) return rc;
     if ((rc = ensure(s->ir_ipiv, (size_t)n * sizeof(int)))) return rc;
@@ -95,6 +118,8 @@ int fp64_path(DeviceState* s, int n, int nrhs, const double* A, long long lda, c
     int* ipiv = reinterpret_cast<int*>(s->ir_ipiv.ptr);
     if (launch_copy_f64(A, lda, A64, n, n, n, stream)) return LU_ERR_HIP;
     if ((rc = factor_impl(n, A64, n, LU_FP64, ipiv, nullptr, nullptr, stream))) return rc;
+    if ((rc = factor_status(s, stream, info))) return rc;
+    if (*info != 0) return 0;
     if (launch_copy_f64(B, ldb, X, ldx, n, nrhs, stream)) return LU_ERR_HIP;
     if ((rc = solve_with_factor<double>(s, n, nrhs, A64, n, ipiv, X, ldx, stream, false))) return rc;
     return read_err(s, stream);
@@ -118,6 +143,13 @@ int hpl_resid(DeviceState* s, int n, const double* A, long long lda, const doubl
 }
 
 }  // namespace
+
+int ir_outcome(int fp64_info, int fell_back, double resid) {
+    if (fp64_info != 0) return LU_ERR_SINGULAR;
+    if (std::isnan(resid)) return LU_ERR_NONFINITE;
+    if (!(resid <= 16.0)) return LU_IR_RESID_HIGH;
+    return fell_back ? LU_IR_FELL_BACK : LU_IR_OK;
+}
 
 int solve_ir_impl(int n, int nrhs, const double* A, int lda, const double* B, int ldb, double* X, int ldx,
                   lu_precision_t prec, int max_iter, int* iters_out, double* resid_out, hipStream_t stream) {
@@ -148,20 +180,25 @@ int solve_ir_impl(int n, int nrhs, const double* A, int lda, const double* B, in
     int iters_total = 0;
     double worst = 0.0;
     bool converged = true;
-    if (prec == LU_FP64) {
-        if ((rc = fp64_path(s, n, nrhs, A, lda, B, ldb, X, ldx, stream))) return rc;
-        for (int c = 0; c < nrhs; ++c) {
-            double res;
-            if ((rc = hpl_resid(s, n, A, lda, B + (long long)c * ldb, X + (long long)c * ldx, anorm, stream, &res)))
-                return rc;
-            worst = std::max(worst, res);
-            if (!(res <= 16.0)) converged = false;
+    // the FP64 factorization, its solve and the HPL test of every column
+    auto fp64_solution = [&](bool fell_back) -> int {
+        int info = 0;
+        int r = fp64_path(s, n, nrhs, A, lda, B, ldb, X, ldx, stream, &info);
+        if (r) return r;
+        worst = 0.0;
+        if (info == 0) {
+            for (int c = 0; c < nrhs; ++c) {
+                double res;
+                if ((r = hpl_resid(s, n, A, lda, B + (long long)c * ldb, X + (long long)c * ldx, anorm, stream, &res)))
+                    return r;
+                worst = std::isnan(res) || std::isnan(worst) ? NAN : std::max(worst, res);
+            }
         }
-        if (iters_out) *iters_out = 0;
-        if (resid_out) *resid_out = worst;
-        if (std::isnan(worst)) return LU_ERR_NONFINITE;
-        return LU_IR_OK;
-    }
+        if (iters_out) *iters_out = iters_total;
+        if (resid_out) *resid_out = info == 0 ? worst : NAN;
+        return ir_outcome(info, fell_back ? 1 : 0, worst);
+    };
+    if (prec == LU_FP64) return fp64_solution(false);
 
     // low-precision factorization of an FP32 working copy
     if ((rc = ensure(s->ir_a32, (size_t)n * n * sizeof(float)))) return rc;
@@ -172,6 +209,9 @@ int solve_ir_impl(int n, int nrhs, const double* A, int lda, const double* B, in
     float* d32 = reinterpret_cast<float*>(s->ir_x32.ptr);
     if (launch_convert_f64_f32(A, lda, A32, n, n, n, stream)) return LU_ERR_HIP;
     if ((rc = factor_impl(n, A32, n, prec, ipiv, nullptr, nullptr, stream))) return rc;
+    int info_lp = 0;
+    if ((rc = factor_status(s, stream, &info_lp))) return rc;
+    if (info_lp != 0) converged = false;    // a zero pivot in the working precision: straight to FP64
     bool moves_ready = false;
     for (int c = 0; c < nrhs && converged; ++c) {
         const double* b = B + (long long)c * ldb;
@@ -201,17 +241,7 @@ int solve_ir_impl(int n, int nrhs, const double* A, int lda, const double* B, in
         return LU_IR_OK;
     }
     // refinement did not reach the FP64 test: refactor in FP64
-    if ((rc = fp64_path(s, n, nrhs, A, lda, B, ldb, X, ldx, stream))) return rc;
-    worst = 0.0;
-    for (int c = 0; c < nrhs; ++c) {
-        double res;
-        if ((rc = hpl_resid(s, n, A, lda, B + (long long)c * ldb, X + (long long)c * ldx, anorm, stream, &res)))
-            return rc;
-        worst = std::max(worst, res);
-    }
-    if (iters_out) *iters_out = iters_total;
-    if (resid_out) *resid_out = worst;
-    return LU_IR_FELL_BACK;
+    return fp64_solution(true);
 }
 
 int solve_ex_impl(int n, int nrhs, const double* LU, int lda, const int* ipiv, double* B, int ldb,
@@ -252,6 +282,8 @@ int lu_solve(int n, int nrhs, const double* LU, const int* ipiv, double* B) {
     if (!s) return err;
     return lu::read_err(s, nullptr);
 }
+
+int lu_ir_outcome(int fp64_info, int fell_back, double resid) { return lu::ir_outcome(fp64_info, fell_back, resid); }
 
 int lu_solve_ir(int n, int nrhs, const double* A, int lda, const double* B, int ldb, double* X, int ldx,
                 lu_precision_t prec, int max_iter, int* iters_out, double* resid_out, hipStream_t stream) {

@@ -65,6 +65,12 @@ struct DeviceState {
 };
 
 DeviceState* device_state(int* err);
+// Entry of a factorization on `stream`: the library's update, panel and swap
+// streams are ordered after everything already enqueued on `stream` and on
+// each other, and the panel barriers' error words are cleared in between
+// (so one time-out does not make every later panel give up).  Uses 4 events
+// of the ring.
+int begin_factorization(DeviceState* s, hipStream_t stream);
 int ensure_events(DeviceState* s, size_t count);   // grow the event ring to at least count
 void release_all();
 int panel_wgs_for(const DeviceState& s, int m, int panel_cus, bool wide = false);

@@ -18,6 +18,7 @@
 #include "common.hpp"
 #include "kernels.hpp"
 #include "mfma.hpp"
+#include "moves.hpp"
 
 namespace lu {
 
@@ -82,6 +83,7 @@ __global__ __launch_bounds__(kThreads, 2) void swap_trsm_kernel(SwapTrsmArgs<T, 
     __shared__ T Xi[2][16][LDX];       // finished block row i (double-buffered)
     __shared__ T Ys[16][LDX];          // owner's staging of block row i before inv(L_ii)
     __shared__ unsigned colmax[BN];
+    __shared__ int ex_count;
 
     const int tid = threadIdx.x;
     const int wave = tid / 64, lane = tid % 64;
@@ -93,16 +95,29 @@ __global__ __launch_bounds__(kThreads, 2) void swap_trsm_kernel(SwapTrsmArgs<T, 
     T* __restrict__ Atop = a.A + a.r0;                  // row r0 of column 0
     const T* __restrict__ L = a.A + a.r0 + (long long)a.r0 * lda;   // L11 at (r0, r0)
 
-    const int ntop = a.moves[0], nex = a.moves[1];
+    // the list is read defensively (moves.hpp): counts clamped, moves outside
+    // the block dropped
+    const int ntop = moves_top_count(a.moves, w);
+    int nex = 0;
+    const int mrows = a.m;
     for (int t = tid; t < w; t += kThreads) top_src[t] = t;
+    if (tid == 0) ex_count = 0;
     __syncthreads();
-    for (int s = tid; s < ntop; s += kThreads) top_src[a.moves[2 + 2 * s]] = a.moves[3 + 2 * s];
-    for (int s = tid; s < nex; s += kThreads) {
-        ex_dst[s] = a.moves[kMovesExtra + 2 * s];
-        ex_src[s] = a.moves[kMovesExtra + 1 + 2 * s];
+    for (int s = tid; s < ntop; s += kThreads) {
+        int dst, src;
+        if (moves_top(a.moves, s, w, mrows, dst, src)) top_src[dst] = src;
+    }
+    for (int s = tid; s < moves_extra_count(a.moves, w); s += kThreads) {
+        int dst, src;
+        if (moves_extra(a.moves, s, w, mrows, dst, src)) {
+            const int slot = atomicAdd(&ex_count, 1);
+            ex_dst[slot] = dst;
+            ex_src[slot] = src;
+        }
     }
     if (tid < BN) colmax[tid] = 0u;
     __syncthreads();
+    nex = ex_count;
 
     // 1. gather into the accumulators: lane (l16, lg), register r of tile
     //    (q, ct) holds X[row = (wave + 4q)*16 + l16][col = ct*16 + Acc::col(lg, r)]
@@ -284,19 +299,34 @@ __global__ __launch_bounds__(kThreads, 2) void swap_trsm_kernel(SwapTrsmArgs<T, 
 }
 
 // Interchanges only, on columns [c0, c1): all reads of a column before its writes.
+// The list is read as in swap_trsm_kernel (rows relative to r0, m rows from there).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void lswap_kernel(T* A, long long lda, int r0, const int* moves, int c0,
-                                                         int c1, int cols_per_wg) {
+__global__ __launch_bounds__(kThreads) void lswap_kernel(T* A, long long lda, int r0, int w, int m, const int* moves,
+                                                         int c0, int c1, int cols_per_wg) {
     __shared__ int mv[2 * 2 * kMovesMaxW];   // (dst, src) pairs, top then extra
     const int tid = threadIdx.x;
-    const int ntop = moves[0], nex = moves[1];
-    const int cnt = ntop + nex;
-    for (int s = tid; s < ntop; s += kThreads) { mv[2 * s] = moves[2 + 2 * s]; mv[2 * s + 1] = moves[3 + 2 * s]; }
-    for (int s = tid; s < nex; s += kThreads) {
-        mv[2 * (ntop + s)] = moves[kMovesExtra + 2 * s];
-        mv[2 * (ntop + s) + 1] = moves[kMovesExtra + 1 + 2 * s];
+    __shared__ int cnt_s;
+    if (tid == 0) cnt_s = 0;
+    __syncthreads();
+    // the list is read defensively (moves.hpp): moves outside the block are dropped
+    for (int s = tid; s < moves_top_count(moves, w); s += kThreads) {
+        int dst, src;
+        if (moves_top(moves, s, w, m, dst, src)) {
+            const int slot = atomicAdd(&cnt_s, 1);
+            mv[2 * slot] = dst;
+            mv[2 * slot + 1] = src;
+        }
+    }
+    for (int s = tid; s < moves_extra_count(moves, w); s += kThreads) {
+        int dst, src;
+        if (moves_extra(moves, s, w, m, dst, src)) {
+            const int slot = atomicAdd(&cnt_s, 1);
+            mv[2 * slot] = dst;
+            mv[2 * slot + 1] = src;
+        }
     }
     __syncthreads();
+    const int cnt = cnt_s;
     constexpr int kPer = (2 * kMovesMaxW + kThreads - 1) / kThreads;
     const int cb = c0 + blockIdx.x * cols_per_wg;
     for (int c = cb; c < min(c1, cb + cols_per_wg); ++c) {
@@ -437,11 +467,13 @@ template int launch_diag_inv<double>(const double*, long long, int, int, double*
 template int launch_diag_inv<float>(const float*, long long, int, int, float*, hipStream_t);
 
 template <typename T>
-int launch_lswap(T* A, long long lda, int r0, const int* moves, int c0, int c1, hipStream_t stream) {
-    if (c1 <= c0) return 0;
+int launch_lswap(T* A, long long lda, int r0, int w, int m, const int* moves, int c0, int c1, hipStream_t stream) {
+    if (c1 <= c0 || m <= 0) return 0;
+    if (w < 1 || w > kMovesMaxW) return -1;
     const int per = 4;
     const int grid = (c1 - c0 + per - 1) / per;
-    hipLaunchKernelGGL((lswap_kernel<T>), dim3(grid), dim3(kThreads), 0, stream, A, lda, r0, moves, c0, c1, per);
+    hipLaunchKernelGGL((lswap_kernel<T>), dim3(grid), dim3(kThreads), 0, stream, A, lda, r0, w, m, moves, c0, c1,
+                       per);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -471,8 +503,8 @@ int launch_l21_half(const float* A, long long lda, int m, int w, H* Lh, long lon
 template int launch_swap_trsm<double, _Float16>(const SwapTrsmArgs<double, _Float16>&, hipStream_t);
 template int launch_swap_trsm<float, _Float16>(const SwapTrsmArgs<float, _Float16>&, hipStream_t);
 template int launch_swap_trsm<float, __bf16>(const SwapTrsmArgs<float, __bf16>&, hipStream_t);
-template int launch_lswap<double>(double*, long long, int, const int*, int, int, hipStream_t);
-template int launch_lswap<float>(float*, long long, int, const int*, int, int, hipStream_t);
+template int launch_lswap<double>(double*, long long, int, int, int, const int*, int, int, hipStream_t);
+template int launch_lswap<float>(float*, long long, int, int, int, const int*, int, int, hipStream_t);
 template int launch_l21_half<_Float16>(const float*, long long, int, int, _Float16*, long long, float*,
                                        hipStream_t);
 template int launch_l21_half<__bf16>(const float*, long long, int, int, __bf16*, long long, float*, hipStream_t);

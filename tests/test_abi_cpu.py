@@ -341,3 +341,69 @@ def test_interchange_free_plan_executes_to_the_qr_oracle(starts, depth):
             _run_qr_task(A, tau, tasks[i], starts)
         assert np.abs(A - oF).max() <= 1e-12
         assert np.abs(tau - otau).max() <= 1e-13
+
+
+def test_refinement_outcome_mapping():
+    """lu_solve_ir's final status (host logic, no device call): a singular FP64
+    factor is an error, a non-finite residual is reported as such, a residual
+    above the HPL bound of 16 is flagged, and the fall-back is distinguished
+    from plain convergence."""
+    lib = lu.load()
+    nan = float("nan")
+    assert lib.lu_ir_outcome(0, 0, 0.05) == lu.LU_IR_OK
+    assert lib.lu_ir_outcome(0, 0, 16.0) == lu.LU_IR_OK
+    assert lib.lu_ir_outcome(0, 1, 0.05) == lu.LU_IR_FELL_BACK
+    assert lib.lu_ir_outcome(0, 0, 16.5) == lu.LU_IR_RESID_HIGH
+    assert lib.lu_ir_outcome(0, 1, 1e30) == lu.LU_IR_RESID_HIGH
+    assert lib.lu_ir_outcome(0, 0, nan) == lu.LU_ERR_NONFINITE
+    assert lib.lu_ir_outcome(0, 1, float("inf")) == lu.LU_IR_RESID_HIGH
+    assert lib.lu_ir_outcome(7, 0, 0.0) == lu.LU_ERR_SINGULAR
+    assert lib.lu_ir_outcome(1, 1, nan) == lu.LU_ERR_SINGULAR
+
+
+def test_garbage_interchange_lists_stay_in_bounds():
+    """The trailing kernels read a panel's composed interchange list through
+    the functions lu_k_moves_check runs on the host: whatever the list holds
+    (an empty one from a panel that gave up at a barrier time-out, stale or
+    random words), every kept move addresses rows inside the block, so the
+    kernels' LDS indices and matrix rows stay in range."""
+    lib = lu.load()
+    MAXW = 512
+    LEN = 2 + 4 * MAXW
+    rng = np.random.default_rng(7)
+    out = np.zeros(4 * MAXW, dtype=np.int32)
+    # an empty list keeps nothing
+    mv = np.zeros(LEN, dtype=np.int32)
+    assert lib.lu_k_moves_check(mv.ctypes.data, 256, 1000, out.ctypes.data) == 0
+    for trial in range(300):
+        w = int(rng.integers(1, MAXW + 1))
+        m = int(rng.integers(w, 70000))
+        kind = trial % 3
+        if kind == 0:          # random words, including huge and negative counts
+            mv = rng.integers(-2 ** 31, 2 ** 31 - 1, LEN, dtype=np.int64).astype(np.int32)
+        elif kind == 1:        # plausible counts, rows slightly out of range
+            mv = rng.integers(-3, m + 3, LEN).astype(np.int32)
+            mv[0] = rng.integers(0, 2 * MAXW)
+            mv[1] = rng.integers(0, 2 * MAXW)
+        else:                  # counts beyond the width
+            mv = rng.integers(0, m, LEN).astype(np.int32)
+            mv[0] = MAXW + 5
+            mv[1] = -1
+        r = lib.lu_k_moves_check(mv.ctypes.data, w, m, out.ctypes.data)
+        assert r >= 0
+        nt, ne = r >> 16, r & 0xFFFF
+        assert nt <= w and ne <= w
+        top = out[:2 * nt].reshape(-1, 2)
+        ext = out[2 * nt:2 * (nt + ne)].reshape(-1, 2)
+        assert np.all((top[:, 0] >= 0) & (top[:, 0] < w) & (top[:, 1] >= 0) & (top[:, 1] < m))
+        assert np.all((ext[:, 0] >= w) & (ext[:, 0] < m) & (ext[:, 1] >= 0) & (ext[:, 1] < w))
+    # a well-formed list from the composition is kept whole
+    w, m = 4, 10
+    piv = np.array([7, 1, 9, 3], dtype=np.int32)      # swaps (0,7), (2,9)
+    mv = np.zeros(LEN, dtype=np.int32)
+    mv[0], mv[1] = 2, 2
+    mv[2:6] = [0, 7, 2, 9]
+    mv[2 + 2 * MAXW:2 + 2 * MAXW + 4] = [7, 0, 9, 2]
+    r = lib.lu_k_moves_check(mv.ctypes.data, w, m, out.ctypes.data)
+    assert (r >> 16, r & 0xFFFF) == (2, 2)
+    assert out[:8].tolist() == [0, 7, 2, 9, 7, 0, 9, 2]

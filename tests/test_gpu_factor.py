@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import synth
-from tests import pins
+from tests import pins, residuals
 
 pytestmark = pytest.mark.gpu
 
@@ -235,23 +235,8 @@ def test_8192_lookahead_and_solve(gpu):
 
 
 def _device_residual(gpu, dA0, dLU, ipiv):
-    """||P A - L U||_F / (||A||_F n eps), computed with torch's FP64 GEMM in
-    column slabs so that only one n x slab product is alive at a time."""
-    import torch
-    n = dA0.shape[0]
-    perm = torch.tensor(oracle.perm_from_ipiv(ipiv), device="cuda")
-    L = torch.tril(dLU, -1)
-    L.diagonal().fill_(1.0)
-    acc = 0.0
-    slab = 4096
-    for c0 in range(0, n, slab):
-        c1 = min(n, c0 + slab)
-        U = torch.triu(dLU[:, c0:c1], diagonal=-c0)[:c1, :]      # rows < c1 of U's columns c0..c1
-        R = dA0[perm, c0:c1] - L[:, :c1] @ U
-        acc += float((R * R).sum().item())
-        del U, R
-    del L
-    return acc ** 0.5 / (torch.linalg.norm(dA0).item() * n * 2.0 ** -53)
+    """||P A - L U||_F / (||A||_F n eps) on the device (tests/residuals.py)."""
+    return residuals.factor_residual(dA0, dLU, ipiv)
 
 
 @pytest.mark.timeout(900)

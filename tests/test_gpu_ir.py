@@ -2,6 +2,8 @@
 the GPU: the refined solution meets the HPL acceptance test, agrees with the
 oracle's FP64 solution within the conditioning bound, and falls back to an
 FP64 factorization when refinement cannot converge."""
+import os
+
 import numpy as np
 import pytest
 
@@ -95,24 +97,108 @@ def test_ir_rejects_nonfinite_input(gpu):
     assert st == gpu.LU_ERR_NONFINITE
 
 
-@pytest.mark.timeout(600)
-def test_mixed_fp16_ir_n32768(gpu):
-    """C4(a) at full size: FP16 trailing GEMM, FP32 panel/TRSM, FP64 refinement.
-    The residual is recomputed independently with torch's FP64 matrix-vector
-    product; the oracle's solution is out of reach at this size."""
+def test_ir_singular_matrix_reported(gpu):
+    """A zero column makes the FP64 factor singular (INFO = its index + 1): the
+    plain FP64 path and the mixed path (whose fall-back refactors in FP64)
+    return LU_ERR_SINGULAR and a NaN residual instead of a solution."""
+    A = synth.uniform(300, seed=13)
+    A[:, 41] = 0.0
+    b = synth.rhs(300, seed=13)[:, 0]
+    for prec in (gpu.LU_FP64, gpu.LU_MIXED_FP16, gpu.LU_FP32):
+        st, it, res, _ = _ir(gpu, A, b, prec)
+        assert st == gpu.LU_ERR_SINGULAR, (prec, st)
+        assert np.isnan(res)
+
+
+# ---- full size (n = 32768), against the oracle's cached FP64 solution -------
+
+def _xo(workload):
+    """The oracle's solution of the seed-1 n = 32768 system of `workload`,
+    written by tests/golden/make_xo.py, and its metadata."""
+    import json
+    from tests.golden import make_xo
+    npy, js = make_xo.paths(workload, 32768, 1)
+    if not os.path.exists(npy):
+        pytest.fail("oracle solution %s missing: run tests/golden/make_xo.py %s" % (npy, workload))
+    with open(js) as f:
+        meta = json.load(f)
+    return np.load(npy), meta
+
+
+_BIG = {}
+
+
+def _big_system(gpu, workload):
+    """Seeded n = 32768 system on the device, checked against the fingerprint
+    of the matrix the oracle solved (kept for the module: 8.6 GB each)."""
+    import torch
+    from tests.golden import make_xo
+    if workload not in _BIG:
+        xo, meta = _xo(workload)
+        A = make_xo.make_matrix(workload, 32768, 1)
+        assert make_xo.check_fingerprint(A, meta["fingerprint"]), "regenerated matrix differs"
+        dA = gpu.to_device(A)
+        del A
+        b = synth.rhs(32768, seed=1)[:, 0]
+        _BIG.clear()
+        _BIG[workload] = (dA, torch.from_numpy(b).cuda(), xo, meta)
+        torch.cuda.synchronize()
+    return _BIG[workload]
+
+
+def _check_full_size_ir(gpu, workload, prec, kappa):
     import torch
     n = 32768
-    A = synth.dominant(n, seed=1)
-    b = synth.rhs(n, seed=1)[:, 0]
-    dA = gpu.to_device(A)
-    del A
-    dB = torch.from_numpy(b).cuda()
+    dA, dB, xo, meta = _big_system(gpu, workload)
     dX = torch.zeros(n, dtype=torch.float64, device="cuda")
-    st, it, res = gpu.lu_solve_ir(dA, dB, dX, prec=2, max_iter=10)
+    print("case", workload, prec, flush=True)
+    st, it, res = gpu.lu_solve_ir(dA, dB, dX, prec=prec, max_iter=20)
     torch.cuda.synchronize()
-    assert st == gpu.LU_IR_OK and it <= 10
+    assert st == gpu.LU_IR_OK and 1 <= it <= 20, (st, it, res)
+    # the HPL residual recomputed with torch's FP64 matrix-vector product
     r = torch.mv(dA, dX) - dB
     anorm = dA.abs().sum(dim=1).max().item()
     rh = r.abs().max().item() / (EPS * (anorm * dX.abs().max().item() + dB.abs().max().item()) * n)
     assert rh <= 16.0
     assert abs(rh - res) <= 1.0 + 2.0 / n       # evaluation rounding of b - A x, as above
+    # forward error against the oracle: both solutions pass the HPL test, so
+    # ||x - x_o|| / ||x_o|| <= 2 * 16 * n * eps * kappa_inf(A)
+    x = dX.cpu().numpy()
+    err = np.abs(x - xo).max() / np.abs(xo).max()
+    assert err <= 2 * 16 * n * EPS * kappa, err
+    return it, err
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", [2, 3])         # FP16 and BF16 trailing updates
+def test_mixed_ir_n32768_against_oracle(gpu, prec):
+    """C4(a) at full size: FP16/BF16 trailing GEMM, FP32 panel and TRSM, FP64
+    refinement on the row-dominant matrix.  Its kappa_inf is about 2 (A = D + R
+    with D = diag of about n/2 and R of random signs, ||D^-1 R||_2 ~ 4/sqrt(n));
+    the bound uses 4."""
+    _check_full_size_ir(gpu, "dominant", prec, kappa=4.0)
+
+
+@pytest.mark.timeout(900)
+def test_fp32_ir_n32768_against_oracle(gpu):
+    """C4(b) at full size: FP32 LU of the non-dominant uniform matrix, FP64
+    refinement.  kappa_inf(A) is out of reach at this size, so the yardstick is
+    the FP64 LU solution of the same system on the GPU: the refined solution's
+    error against the oracle must stay within 16 times that solution's error
+    (or 16 times the bound 2 * 16 n eps, if that is larger)."""
+    import torch
+    n = 32768
+    dA, dB, xo, meta = _big_system(gpu, "uniform")
+    it, err = None, None
+    # FP64 solution on the GPU: factor a copy, solve
+    LU = dA.clone()
+    ipiv = torch.zeros(n, dtype=torch.int32, device="cuda")
+    assert gpu.lu_factor_ex(LU, ipiv, prec=gpu.LU_FP64) == 0
+    x64 = dB.clone().reshape(n, 1)
+    assert gpu.lu_solve_ex(LU, ipiv, x64) == 0
+    torch.cuda.synchronize()
+    del LU
+    e64 = np.abs(x64.cpu().numpy()[:, 0] - xo).max() / np.abs(xo).max()
+    kappa = 16 * max(1.0, e64 / (2 * 16 * n * EPS))     # bound = 16 max(e64, 2 * 16 n eps)
+    it, err = _check_full_size_ir(gpu, "uniform", gpu.LU_FP32, kappa=kappa)
+    print("fp32+IR n=32768: iterations %d, error %.3e (FP64 LU error %.3e)" % (it, err, e64))

@@ -145,3 +145,51 @@ def test_laswp_exact(gpu, m, w):
     for t in range(w):
         want[[t, piv[t]], :] = want[[piv[t], t], :]
     assert np.array_equal(gpu.to_host(dC), want)
+
+
+WIDE_CHILD = r"""
+import sys
+sys.path.insert(0, %r)
+import numpy as np
+import torch
+import paper_1804_07017_amd as lu
+import synth
+lu.load()
+m, w, out = %d, %d, %r
+A = synth.uniform(m, seed=m + w)
+P = lu.to_device(np.array(A[:, :w], order="F"), torch.float64, lda=m + 5)
+piv = torch.zeros(w, dtype=torch.int32, device="cuda")
+print("case wide panel m=%%d w=%%d" %% (m, w), flush=True)
+rc = lu.lu_k_panel(P, piv, prec=0, wgs=1)
+torch.cuda.synchronize()
+np.save(out + "/lu.npy", lu.to_host(P))
+np.save(out + "/piv.npy", piv.cpu().numpy())
+print("rc", rc, flush=True)
+"""
+
+
+@pytest.mark.parametrize("m,w", [(4096, 256), (3000, 200)])
+def test_wide_fp64_panel_matches_oracle(gpu, tmp_path, m, w):
+    """The FP64 panel variant for tall panels (1024 rows per work-group, its
+    finished columns re-read from memory instead of an LDS copy), which
+    factors the panels taller than LU_WIDE_ROWS rows (20480 by default).  A
+    child process lowers that threshold to 512 rows so the variant runs at a
+    size the oracle finishes quickly; the result is compared element by
+    element, as for the other panel variants."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, LU_WIDE_ROWS="512")
+    r = subprocess.run([sys.executable, "-c", WIDE_CHILD % (root, m, w, str(tmp_path))], env=env,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and "rc 0" in r.stdout, (r.stdout[-2000:], r.stderr[-2000:])
+    got = np.load(str(tmp_path / "lu.npy"))
+    gp = np.load(str(tmp_path / "piv.npy"))
+    A = synth.uniform(m, seed=m + w)
+    LU, ipiv, _ = oracle.getrf(A, nthreads=8)
+    assert np.array_equal(gp, ipiv[:w])
+    for t in range(w, m):
+        if ipiv[t] != t:
+            got[[t, ipiv[t]], :] = got[[ipiv[t], t], :]
+    assert np.abs(got - LU[:, :w]).max() <= 1e-12 * max(1.0, np.abs(LU[:, :w]).max())
