@@ -75,6 +75,14 @@ int lu_k_moves_check(const int* moves, int w, int m, int* out);
  *   resid > 16 -> LU_IR_RESID_HIGH;  else LU_IR_FELL_BACK or LU_IR_OK. */
 int lu_ir_outcome(int fp64_info, int fell_back, double resid);
 
+/* Diagnostic: the XCD (hardware register XCC_ID) that each of work-groups
+ * 0..63 of one launch runs on, written to out (host int[64]).  Returns 1 if
+ * work-group b runs on XCD (b + c) % 8 for one offset c -- the round-robin
+ * deal the library's XCD-island schedule relies on (8 P work-groups put P on
+ * each XCD), checked once per device when the library first uses it -- 0 if
+ * not, or LU_ERR_HIP. */
+int lu_k_xcd_probe(int* out);
+
 /* Diagnostic: run one v_mfma_f64_16x16x4f64 on lane-indexed inputs
  * (a = lane, b = 100 + lane, c = 0) and write the 64x4 outputs to out (device
  * double[256], lane-major). */

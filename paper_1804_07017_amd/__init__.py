@@ -75,6 +75,7 @@ _SIGS = {
     "lu_k_probe_mfma_f64": (_I, [_P, _P]),
     "lu_ir_outcome": (_I, [_I, _I, ctypes.c_double]),
     "lu_k_moves_check": (_I, [_P, _I, _I, _P]),
+    "lu_k_xcd_probe": (_I, [_P]),
     "lu_k_timing": (_I, [_I]),
     "lu_k_timing_read": (_I, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(_I)]),

@@ -55,6 +55,7 @@ int timed_begin(hipStream_t st, int M, int N, int K, hipEvent_t* stop) {
     return hipEventRecord(start, st) == hipSuccess ? 0 : LU_ERR_HIP;
 }
 constexpr int kEventRing = 1024;
+constexpr int kClaimWords = 16 + 2 * 3;   // GEMM: 2 x 8 chunk counters; swap+TRSM and left swaps: 2 each
 constexpr int kMaxCand = 256;       // max panel work-groups
 constexpr int kNB = 16;             // panel register block width (panel.hip)
 }  // namespace
@@ -88,6 +89,17 @@ void release(Buffer& b) {
     if (b.ptr) hipFree(b.ptr);
     b.ptr = nullptr;
     b.bytes = 0;
+}
+
+// XCD of work-groups 0..63 of one launch (out: host int[64]); 0 or LU_ERR_HIP.
+int probe_xcds(int* out) {
+    int* d = nullptr;
+    (void)hipGetLastError();          // a stale error of an earlier call must not fail this check
+    if (hipMalloc(&d, 64 * sizeof(int)) != hipSuccess) return LU_ERR_HIP;
+    int rc = launch_xcd_probe(d, 64, nullptr);
+    if (rc == 0 && hipMemcpy(out, d, 64 * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) rc = LU_ERR_HIP;
+    hipFree(d);
+    return rc == 0 ? 0 : LU_ERR_HIP;
 }
 
 DeviceState* device_state(int* err) {
@@ -134,6 +146,17 @@ DeviceState* device_state(int* err) {
     if (hipMemset(s->sync, 0, 8 * sizeof(unsigned)) != hipSuccess) { *err = LU_ERR_HIP; return nullptr; }
     if (hipMalloc(&s->info, 4 * sizeof(int)) != hipSuccess) { *err = LU_ERR_NOMEM; return nullptr; }
     if (hipMemset(s->info, 0, 4 * sizeof(int)) != hipSuccess) { *err = LU_ERR_HIP; return nullptr; }
+    // the one-XCD panel placement needs the work-groups of a launch dealt
+    // round-robin to the 8 XCDs (work-group b on XCD (b + offset) % 8, the
+    // offset varying from launch to launch), so that 8 P of them put P on each
+    // XCD: probe it once
+    if (s->num_cus % 8 == 0) {
+        int h[64];
+        s->xcd_round_robin = probe_xcds(h) == 0 ? 1 : 0;
+        for (int b = 0; b < 64; ++b) s->xcd_round_robin &= ((h[b] - h[0] - b) % 8 + 8) % 8 == 0 ? 1 : 0;
+    }
+    if (const char* e = std::getenv("LU_PANEL_XCD")) s->panel_one_xcd = std::atoi(e) > 0 ? 1 : 0;
+    if (const char* e = std::getenv("LU_ISLAND")) s->island = std::atoi(e) > 0 ? 1 : 0;
     // tagged exchange area of the panel kernel (sized for FP64 and the maximum work-group count)
     if (ensure(s->cand, (size_t)kPanelXchWords * sizeof(unsigned long long))) { *err = LU_ERR_NOMEM; return nullptr; }
     if (hipMemset(s->cand.ptr, 0, s->cand.bytes) != hipSuccess) { *err = LU_ERR_HIP; return nullptr; }
@@ -177,7 +200,7 @@ void release_all() {
         if (s->swap_stream) hipStreamDestroy(s->swap_stream);
         if (s->sync) hipFree(s->sync);
         if (s->info) hipFree(s->info);
-        Buffer* bufs[] = {&s->cand, &s->moves, &s->linv, &s->lh, &s->uh, &s->rs, &s->cs, &s->solve_moves, &s->flags,
+        Buffer* bufs[] = {&s->claims, &s->cand, &s->moves, &s->linv, &s->lh, &s->uh, &s->rs, &s->cs, &s->solve_moves, &s->flags,
                           &s->partial, &s->ir_r, &s->ir_x32, &s->ir_a32, &s->ir_a64, &s->ir_norms, &s->ir_ipiv,
                           &s->ir_b, &s->qr_v, &s->qr_vt, &s->qr_t, &s->qr_tt, &s->qr_w, &s->qr_ws, &s->qr_ym, &s->qr_part,
                           &s->band_z, &s->band_v, &s->band_vt, &s->band_t, &s->band_tt, &s->band_w,
@@ -257,9 +280,12 @@ const DeviceState::Plan* get_plan(DeviceState* s, int n, const lu_schedule_t& sc
 struct HalfNone {};
 
 
+// island: the factorization keeps XCD 0 for its panels (every panel on at
+// most num_cus / 8 work-groups of up to 1024 rows, on XCD 0) while the bulk
+// update runs on the other XCDs.
 template <typename T>
 int run_panel(DeviceState* s, T* A, long long lda, int n, int j0, int w, int* ipiv, int* info, int* moves,
-              int wgs_req, hipStream_t st) {
+              int wgs_req, hipStream_t st, bool island = false) {
     PanelArgs<T> pa;
     const int m = n - j0;
     pa.A = A + j0 + (long long)j0 * lda;
@@ -287,9 +313,14 @@ int run_panel(DeviceState* s, T* A, long long lda, int n, int j0, int w, int* ip
     pa.spin_limit = s->spin_limit;
     pa.occupancy = s->panel_occupancy;
     // tall FP64 panels (m > wide_rows) use 4*threads rows per group
-    const bool wide = sizeof(T) == 8 && m > s->wide_rows;
-    int wgs = panel_wgs_for(*s, m, wgs_req, wide);
+    const int per_xcd = s->num_cus / 8;
+    const bool wide = (sizeof(T) == 8 && m > s->wide_rows) || (island && m > per_xcd * 2 * panel_threads());
+    int wgs = panel_wgs_for(*s, m, island ? std::min(wgs_req, per_xcd) : wgs_req, wide);
     if (wgs < 0) return LU_ERR_UNSUPPORTED;
+    if (island && wgs > per_xcd) return LU_ERR_UNSUPPORTED;
+    pa.one_xcd = ((island || s->panel_one_xcd) && s->xcd_round_robin && wgs <= per_xcd) ? 1 : 0;
+    pa.rank = s->sync + 5;                 // cleared right before the launch, on its stream
+    if (pa.one_xcd && launch_fill_zero(pa.rank, sizeof(unsigned), st)) return LU_ERR_HIP;
     return launch_panel<T>(pa, wgs, st) == 0 ? 0 : LU_ERR_HIP;
 }
 
@@ -330,6 +361,32 @@ int execute(DeviceState* s, int n, T* A, long long lda, int* ipiv, int* info, co
     // the left interchanges are ordered on the update stream: run beside the
     // panel they slow it down more than they gain
     hipStream_t streams[kPlanStreams] = {s->update_stream, s->panel_stream, s->update_stream};
+    // XCD island: with look-ahead, every panel runs on XCD 0 and the kernels of
+    // the update stream leave XCD 0 free, so a panel never waits for the CUs
+    // of a long trailing update (a panel work-group needs a whole CU)
+    const bool island = s->island && sch.depth >= 1 && s->xcd_round_robin &&
+                        (long long)n <= (long long)(s->num_cus / 8) * 4 * panel_threads();
+    if (island && !s->claims.ptr) {
+        if ((rc = ensure(s->claims, kClaimWords * sizeof(unsigned)))) return rc;
+        LU_HIP(hipMemset(s->claims.ptr, 0, s->claims.bytes));
+    }
+    unsigned* claims = reinterpret_cast<unsigned*>(s->claims.ptr);
+    // counters of the XCD-0-free launches on the update stream: ping-pong pairs,
+    // each launch clears its successor's (the previous user has finished)
+    auto gemm_claim = [&]() {
+        XcdClaim c;
+        c.ctr = claims + 8 * s->claim_par[0];
+        c.next = claims + 8 * (1 - s->claim_par[0]);
+        c.cus = s->num_cus;
+        s->claim_par[0] ^= 1;
+        return c;
+    };
+    auto one_claim = [&](int kind, unsigned** next) {
+        unsigned* c = claims + 16 + 2 * kind + s->claim_par[kind];
+        *next = claims + 16 + 2 * kind + (1 - s->claim_par[kind]);
+        s->claim_par[kind] ^= 1;
+        return c;
+    };
     // entry join: the library streams start after everything already on `stream`
     // and after every earlier task of their own; the panel barriers' error
     // words are cleared in between, so a time-out of an earlier factorization
@@ -349,7 +406,7 @@ int execute(DeviceState* s, int n, T* A, long long lda, int* ipiv, int* info, co
         const int wk = starts[k + 1] - kb;
         int* mv = moves + (size_t)k * kMovesLen;
         if (t.kind == kTaskPanel) {
-            if ((rc = run_panel<T>(s, A, lda, n, kb, wk, ipiv, info, mv, sch.panel_cus, st))) return rc;
+            if ((rc = run_panel<T>(s, A, lda, n, kb, wk, ipiv, info, mv, sch.panel_cus, st, island))) return rc;
             if (launch_diag_inv<T>(A, lda, kb, wk, linv + (size_t)k * kLinvPer, st)) return LU_ERR_HIP;
             if (mixed && n - kb - wk > 0) {
                 if (launch_l21_half<H>(reinterpret_cast<const float*>(A) + (kb + wk) + (long long)kb * lda, lda,
@@ -364,6 +421,9 @@ int execute(DeviceState* s, int n, T* A, long long lda, int* ipiv, int* info, co
             sa.uh = mixed ? Uh + kb : nullptr;
             sa.lduh = lduh;
             sa.cs = mixed ? cs + (size_t)k * n : nullptr;
+            const bool skip_t = island && t.stream != 1;     // panel-stream work may use XCD 0
+            sa.claim = skip_t ? one_claim(1, &sa.claim_next) : nullptr;
+            if (!skip_t) sa.claim_next = nullptr;
             if (launch_swap_trsm<T, H>(sa, st)) return LU_ERR_HIP;
             const int M = n - kb - wk, Nc = t.col_end - t.col_begin;
             if (M > 0) {
@@ -372,20 +432,23 @@ int execute(DeviceState* s, int n, T* A, long long lda, int* ipiv, int* info, co
                                             Uh + (long long)t.col_begin * lduh + kb, (int)lduh,
                                             rs + (size_t)k * n + (kb + wk), cs + (size_t)k * n + t.col_begin,
                                             reinterpret_cast<float*>(A) + (kb + wk) + (long long)t.col_begin * lda,
-                                            (int)lda, st))
+                                            (int)lda, st, skip_t ? gemm_claim() : XcdClaim()))
                         return LU_ERR_HIP;
                 } else {
                     hipEvent_t stop;
                     if ((rc = timed_begin(st, M, Nc, wk, &stop))) return rc;
                     if (launch_gemm<T>(M, Nc, wk, A + (kb + wk) + (long long)kb * lda, (int)lda,
                                        A + kb + (long long)t.col_begin * lda, (int)lda,
-                                       A + (kb + wk) + (long long)t.col_begin * lda, (int)lda, st))
+                                       A + (kb + wk) + (long long)t.col_begin * lda, (int)lda, st,
+                                       skip_t ? gemm_claim() : XcdClaim()))
                         return LU_ERR_HIP;
                     if (stop) LU_HIP(hipEventRecord(stop, st));
                 }
             }
         } else {
-            if (launch_lswap<T>(A, lda, kb, wk, n - kb, mv, t.col_begin, t.col_end, st)) return LU_ERR_HIP;
+            unsigned* nx = nullptr;
+            unsigned* cl = island ? one_claim(2, &nx) : nullptr;
+            if (launch_lswap<T>(A, lda, kb, wk, n - kb, mv, t.col_begin, t.col_end, st, cl, nx)) return LU_ERR_HIP;
         }
         if (t.record) {
             const int e = s->ev_next;
@@ -549,7 +612,7 @@ int lu_k_update(lu_precision_t prec, int m, int w, int ncols, const void* L, int
         double* A = const_cast<double*>(reinterpret_cast<const double*>(L));
         double* linv = reinterpret_cast<double*>(s->linv.ptr);
         if (lu::launch_diag_inv<double>(A, ldl, 0, w, linv, stream)) return LU_ERR_HIP;
-        lu::SwapTrsmArgs<double, _Float16> sa{A, ldl, 0, w, mv, m, c0, c0 + ncols, linv, nullptr, 0, nullptr};
+        lu::SwapTrsmArgs<double, _Float16> sa{A, ldl, 0, w, mv, m, c0, c0 + ncols, linv, nullptr, 0, nullptr, 0};
         if (lu::launch_swap_trsm<double, _Float16>(sa, stream)) return LU_ERR_HIP;
         if (m > w && lu::launch_gemm<double>(m - w, ncols, w, A + w, ldl, A + (long long)c0 * ldl, ldl,
                                              A + w + (long long)c0 * ldl, ldl, stream))
@@ -558,7 +621,7 @@ int lu_k_update(lu_precision_t prec, int m, int w, int ncols, const void* L, int
         float* A = const_cast<float*>(reinterpret_cast<const float*>(L));
         float* linv = reinterpret_cast<float*>(s->linv.ptr);
         if (lu::launch_diag_inv<float>(A, ldl, 0, w, linv, stream)) return LU_ERR_HIP;
-        lu::SwapTrsmArgs<float, _Float16> sa{A, ldl, 0, w, mv, m, c0, c0 + ncols, linv, nullptr, 0, nullptr};
+        lu::SwapTrsmArgs<float, _Float16> sa{A, ldl, 0, w, mv, m, c0, c0 + ncols, linv, nullptr, 0, nullptr, 0};
         if (lu::launch_swap_trsm<float, _Float16>(sa, stream)) return LU_ERR_HIP;
         if (m > w && lu::launch_gemm<float>(m - w, ncols, w, A + w, ldl, A + (long long)c0 * ldl, ldl,
                                             A + w + (long long)c0 * ldl, ldl, stream))
@@ -680,6 +743,16 @@ int lu_k_moves_check(const int* moves, int w, int m, int* out) {
         if (lu::moves_extra(moves, s, w, m, d, r)) { out[2 * k] = d; out[2 * k + 1] = r; ++k; }
     }
     return (ktop << 16) | (k - ktop);
+}
+
+int lu_k_xcd_probe(int* out) {
+    if (!out) return -1;
+    int err;
+    lu::DeviceState* s = lu::device_state(&err);
+    if (!s) return err;
+    int rc = lu::probe_xcds(out);
+    if (rc) return rc;
+    return s->xcd_round_robin;
 }
 
 int lu_k_probe_mfma_f64(double* out, hipStream_t stream) {

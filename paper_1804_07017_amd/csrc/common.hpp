@@ -107,6 +107,88 @@ __device__ __forceinline__ T xload(const T* p) {
     return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Scoped, fence-free forms used by the panel kernel.  Every access to data
+// that another work-group of the launch reads or writes is a relaxed atomic
+// at scope S; the panel uses S = __HIP_MEMORY_SCOPE_AGENT, the device
+// coherence point (the per-CU L1 and the per-XCD L2 are bypassed).  Ordering
+// then needs no cache write-back or invalidate (which, at agent scope, act on
+// a whole XCD's L2 and stall the work beside the panel): a writer waits for
+// its own accesses to complete (s_waitcnt) before it signals, and a reader
+// issues its loads after it has seen the signal.
+template <int S>
+__device__ __forceinline__ void xstore_s(unsigned long long* p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, S);
+}
+template <int S>
+__device__ __forceinline__ void xstore_s(unsigned* p, unsigned v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, S);
+}
+template <int S, typename U>
+__device__ __forceinline__ U xload_s(const U* p) {
+    return __hip_atomic_load(const_cast<U*>(p), __ATOMIC_RELAXED, S);
+}
+template <int S>
+__device__ __forceinline__ double cload(const double* p) {
+    return __longlong_as_double((long long)xload_s<S>(reinterpret_cast<const unsigned long long*>(p)));
+}
+template <int S>
+__device__ __forceinline__ float cload(const float* p) {
+    return __uint_as_float(xload_s<S>(reinterpret_cast<const unsigned*>(p)));
+}
+template <int S>
+__device__ __forceinline__ void cstore(double* p, double v) {
+    xstore_s<S>(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v));
+}
+template <int S>
+__device__ __forceinline__ void cstore(float* p, float v) {
+    xstore_s<S>(reinterpret_cast<unsigned*>(p), __float_as_uint(v));
+}
+// This wave's memory accesses have completed (at their scope's coherence
+// point for the scoped atomics above).  The signal fences keep the compiler
+// from moving memory operations across the wait.
+__device__ __forceinline__ void wave_mem_drain() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Barrier among the nwg participating work-groups of one launch, without
+// fences: every wave drains its accesses, then one arrival per work-group on
+// a relaxed counter.  The counter and the error word are shared with launches
+// of either scope, so they are always accessed at the device coherence point
+// (a word must not be updated at one XCD's L2 by one launch and at the
+// device coherence point by another).  The wait is bounded as in grid_barrier.
+__device__ __forceinline__ bool grid_barrier_nofence(unsigned* counter, unsigned* err, unsigned epoch,
+                                                     long long limit, int nwg) {
+    constexpr int A = __HIP_MEMORY_SCOPE_AGENT;
+    __shared__ int s_fail;
+    wave_mem_drain();
+    __syncthreads();
+    if (threadIdx.x == 0 && nwg > 1) {
+        const unsigned target = epoch * (unsigned)nwg;
+        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, A);
+        int fail = 0;
+        const long long t0 = wall_clock64();
+        while (xload_s<A>(counter) < target) {
+            if (xload_s<A>(err) != 0u) { fail = 1; break; }
+            if (wall_clock64() - t0 > limit) {
+                xstore_s<A>(err, 1u);
+                fail = 1;
+                break;
+            }
+        }
+        s_fail = fail;
+    } else if (threadIdx.x == 0) {
+        s_fail = 0;
+    }
+    __syncthreads();
+    return s_fail != 0;
+}
+
+// XCD (accelerator complex die) the calling wave runs on: hardware register
+// XCC_ID, bits [3:0].
+__device__ __forceinline__ int xcd_id() { return __builtin_amdgcn_s_getreg((3 << 11) | 20) & 15; }
+
 // Device-wide barrier among the gridDim.x work-groups of one launch.  All of
 // them must be resident at once (the host sizes the grid for that).  The
 // counter starts at 0 for the launch; barrier number `epoch` (1-based) waits

@@ -17,6 +17,8 @@
 // Element (i,j) of C sees the same sequence of operations whatever the tile
 // it falls in, so splitting the update into several launches (the look-ahead
 // schedule does) leaves the result bit-identical.
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "mfma.hpp"
@@ -38,17 +40,23 @@ constexpr int kBM = 128, kBN = 128, kThreads = 256;
 // the XCDs would leave the first XCDs nearly idle; in plain order every XCD
 // takes every 8th tile, a fair share of the full ones.
 constexpr int kGroupM = 8;
-__device__ __forceinline__ void tile_of(int tiles_m, int tiles_n, int& tm, int& tn, bool xcd_chunks = true) {
-    const int nt = tiles_m * tiles_n;
-    int bid = blockIdx.x;
-    const int per = nt / 8;
-    if (xcd_chunks && per > 0 && bid < per * 8) bid = (bid % 8) * per + bid / 8;
+// Tile order: linear tile L walks kGroupM tile-rows down before moving to the
+// next tile column.
+__device__ __forceinline__ void tile_coords(int L, int tiles_m, int tiles_n, int& tm, int& tn) {
     const int grp = kGroupM * tiles_n;
-    const int gi = bid / grp, r = bid % grp;
+    const int gi = L / grp, r = L % grp;
     const int m0 = gi * kGroupM;
     const int gh = min(kGroupM, tiles_m - m0);
     tm = m0 + r % gh;
     tn = r / gh;
+}
+// One tile per work-group: work-group b runs on XCD b % 8, so b is remapped
+// to give each XCD a contiguous chunk of the tile order.
+__device__ __forceinline__ int tile_of_block(int nt, bool xcd_chunks) {
+    int bid = blockIdx.x;
+    const int per = nt / 8;
+    if (xcd_chunks && per > 0 && bid < per * 8) bid = (bid % 8) * per + bid / 8;
+    return bid;
 }
 
 // The tile body.  TB: B is given transposed (element (k, j) at B[j + k*ldb]),
@@ -57,7 +65,7 @@ __device__ __forceinline__ void tile_of(int tiles_m, int tiles_n, int& tm, int& 
 // (i, j) of C when i + diag >= j -- tiles wholly above it are skipped and
 // tiles across it store only their lower part.
 template <typename T, int BK, bool TB, bool LOW, bool ZERO = false>
-__device__ __forceinline__ void gemm_tile(int M, int N, int K, const T* __restrict__ A, int lda,
+__device__ __forceinline__ void gemm_tile(int L, int M, int N, int K, const T* __restrict__ A, int lda,
                                           const T* __restrict__ B, int ldb, T* __restrict__ C, int ldc,
                                           int diag) {
     typedef typename Acc<T>::type V4;
@@ -67,7 +75,7 @@ __device__ __forceinline__ void gemm_tile(int M, int N, int K, const T* __restri
 
     const int tiles_m = (M + kBM - 1) / kBM, tiles_n = (N + kBN - 1) / kBN;
     int tm, tn;
-    tile_of(tiles_m, tiles_n, tm, tn, !LOW);
+    tile_coords(L, tiles_m, tiles_n, tm, tn);
     const int m0 = tm * kBM, n0 = tn * kBN;
     if constexpr (LOW) {
         if (m0 + kBM - 1 + diag < n0) return;          // the whole tile lies above the diagonal
@@ -216,7 +224,62 @@ template <typename T, int BK>
 __global__ __launch_bounds__(kThreads, 2) void gemm_nn_sub(int M, int N, int K, const T* __restrict__ A,
                                                             int lda, const T* __restrict__ B, int ldb,
                                                             T* __restrict__ C, int ldc) {
-    gemm_tile<T, BK, false, false>(M, N, K, A, lda, B, ldb, C, ldc, 0);
+    const int nt = ((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
+    gemm_tile<T, BK, false, false>(tile_of_block(nt, true), M, N, K, A, lda, B, ldb, C, ldc, 0);
+}
+
+// Tile claiming for a launch beside a panel that holds XCD 0 (the trailing
+// update of the look-ahead).  The work-groups on XCD 0 return at once, so no
+// work-group of the launch waits for, or holds, a CU there.  The tile order is
+// cut into 7 contiguous chunks with one counter each; a work-group on XCD x
+// claims tiles of chunk x - 1 (its XCD's L2 keeps that chunk's operands) and,
+// once that is exhausted, of the other chunks.  Every tile is claimed exactly
+// once whatever the placement.  The next tile is claimed while the current
+// one is computed.  claim[0..7]: counters of this launch; next[0..7]: the next
+// such launch's (its stream's previous launch has finished), cleared here.
+struct TileClaim {
+    unsigned* ctr;
+    unsigned* next;
+    int nt, chunk, home;
+    __device__ __forceinline__ int get() const {      // one thread; -1 when none is left
+        for (int v = 0; v < 7; ++v) {
+            const int c = (home + v) % 7;
+            const int lo = c * chunk, len = min(nt, lo + chunk) - lo;
+            if (len <= 0) continue;
+            if ((int)xload(ctr + c) >= len) continue;
+            const int i = (int)atomicAdd(ctr + c, 1u);
+            if (i < len) return lo + i;
+        }
+        return -1;
+    }
+};
+
+template <typename Body>
+__device__ __forceinline__ void claimed_tiles(unsigned* ctr, unsigned* next, int nt, Body body) {
+    __shared__ int s_tile;
+    if (blockIdx.x == 0 && threadIdx.x < 8) xstore(next + threadIdx.x, 0u);
+    const int x = xcd_id();
+    if (x == 0) return;
+    const TileClaim tc{ctr, next, nt, (nt + 6) / 7, (x - 1) % 7};
+    int ahead = threadIdx.x == 0 ? tc.get() : 0;
+    for (;;) {
+        __syncthreads();                       // every wave has read s_tile of the last round
+        if (threadIdx.x == 0) s_tile = ahead;
+        __syncthreads();
+        const int L = s_tile;
+        if (L < 0) break;
+        if (threadIdx.x == 0) ahead = tc.get();
+        body(L);
+    }
+}
+
+template <typename T, int BK>
+__global__ __launch_bounds__(kThreads, 2) void gemm_nn_sub_x7(int M, int N, int K, const T* __restrict__ A,
+                                                               int lda, const T* __restrict__ B, int ldb,
+                                                               T* __restrict__ C, int ldc, unsigned* ctr,
+                                                               unsigned* next) {
+    const int nt = ((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
+    claimed_tiles(ctr, next, nt, [&](int L) { gemm_tile<T, BK, false, false>(L, M, N, K, A, lda, B, ldb, C, ldc, 0); });
 }
 
 // The same product for the Householder block updates (QR, band reduction):
@@ -225,7 +288,8 @@ template <typename T, int BK>
 __global__ __launch_bounds__(kThreads, 2) void gemm_nn_hh(int M, int N, int K, const T* __restrict__ A,
                                                            int lda, const T* __restrict__ B, int ldb,
                                                            T* __restrict__ C, int ldc) {
-    gemm_tile<T, BK, false, false>(M, N, K, A, lda, B, ldb, C, ldc, 0);
+    const int nt = ((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
+    gemm_tile<T, BK, false, false>(tile_of_block(nt, true), M, N, K, A, lda, B, ldb, C, ldc, 0);
 }
 
 // Split-K form for products with a long k range and few output tiles (the
@@ -240,8 +304,9 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_nn_split(int M, int N, int K
                                                               T* __restrict__ C, int ldc, long long cstride) {
     const int z = blockIdx.y;
     const int k0 = z * ks;
-    gemm_tile<T, BK, false, false, true>(M, N, min(ks, K - k0), A + (long long)k0 * lda, lda, B + k0, ldb,
-                                         C + z * cstride, ldc, 0);
+    const int nt = ((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
+    gemm_tile<T, BK, false, false, true>(tile_of_block(nt, true), M, N, min(ks, K - k0), A + (long long)k0 * lda,
+                                         lda, B + k0, ldb, C + z * cstride, ldc, 0);
 }
 
 // C -= A B^T on the lower triangle of C (the symmetric rank-k update of a
@@ -250,7 +315,7 @@ template <typename T, int BK>
 __global__ __launch_bounds__(kThreads, 2) void syrk_ln_sub(int M, int N, int K, const T* __restrict__ A,
                                                             int lda, const T* __restrict__ B, int ldb,
                                                             T* __restrict__ C, int ldc, int diag) {
-    gemm_tile<T, BK, true, true>(M, N, K, A, lda, B, ldb, C, ldc, diag);
+    gemm_tile<T, BK, true, true>((int)blockIdx.x, M, N, K, A, lda, B, ldb, C, ldc, diag);
 }
 
 // Mixed precision: C (FP32) -= diag(rs) (Ah Bh) diag(cs), Ah = FP16/BF16 rows
@@ -273,11 +338,9 @@ template <> struct HalfOps<__bf16> {
 };
 
 template <typename H>
-__global__ __launch_bounds__(kThreads, 2) void gemm_half_sub(int M, int N, int K, const H* __restrict__ Ah,
-                                                              int lda_h, const H* __restrict__ Bh, int ldb_h,
-                                                              const float* __restrict__ rs,
-                                                              const float* __restrict__ cs,
-                                                              float* __restrict__ C, int ldc) {
+__device__ __forceinline__ void gemm_half_tile(int L, int M, int N, int K, const H* __restrict__ Ah, int lda_h,
+                                               const H* __restrict__ Bh, int ldb_h, const float* __restrict__ rs,
+                                               const float* __restrict__ cs, float* __restrict__ C, int ldc) {
     typedef typename HalfOps<H>::vec VH;
     constexpr int BK = 64;              // two MFMA k-steps of 32
     constexpr int PADH = 8;             // halves of padding per LDS row
@@ -286,7 +349,7 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_half_sub(int M, int N, int K
 
     const int tiles_m = (M + kBM - 1) / kBM, tiles_n = (N + kBN - 1) / kBN;
     int tm, tn;
-    tile_of(tiles_m, tiles_n, tm, tn);
+    tile_coords(L, tiles_m, tiles_n, tm, tn);
     const int m0 = tm * kBM, n0 = tn * kBN;
     const int tid = threadIdx.x;
     const int wave = tid / 64, lane = tid % 64;
@@ -411,15 +474,46 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_half_sub(int M, int N, int K
     }
 }
 
+
+template <typename H>
+__global__ __launch_bounds__(kThreads, 2) void gemm_half_sub(int M, int N, int K, const H* __restrict__ Ah,
+                                                              int lda_h, const H* __restrict__ Bh, int ldb_h,
+                                                              const float* __restrict__ rs,
+                                                              const float* __restrict__ cs,
+                                                              float* __restrict__ C, int ldc) {
+    const int nt = ((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
+    gemm_half_tile<H>(tile_of_block(nt, true), M, N, K, Ah, lda_h, Bh, ldb_h, rs, cs, C, ldc);
+}
+
+// XCD 0 left free, tiles claimed as in gemm_nn_sub_x7
+template <typename H>
+__global__ __launch_bounds__(kThreads, 2) void gemm_half_sub_x7(int M, int N, int K, const H* __restrict__ Ah,
+                                                                 int lda_h, const H* __restrict__ Bh, int ldb_h,
+                                                                 const float* __restrict__ rs,
+                                                                 const float* __restrict__ cs,
+                                                                 float* __restrict__ C, int ldc, unsigned* ctr,
+                                                                 unsigned* next) {
+    const int nt = ((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
+    claimed_tiles(ctr, next, nt, [&](int L) { gemm_half_tile<H>(L, M, N, K, Ah, lda_h, Bh, ldb_h, rs, cs, C, ldc); });
+}
+
 }  // namespace
+
+// Grid of a launch that leaves XCD 0 free: two work-groups per CU (those
+// dealt to XCD 0 return at once), no more than there are tiles plus one round.
+inline int x7_grid(int num_cus, int tiles) { return std::min(2 * num_cus, tiles + tiles / 7 + 8); }
 
 template <typename T>
 int launch_gemm(int M, int N, int K, const T* A, int lda, const T* B, int ldb, T* C, int ldc,
-                hipStream_t stream) {
+                hipStream_t stream, XcdClaim claim) {
     if (M <= 0 || N <= 0 || K <= 0) return 0;
     const int tiles = ((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
-    hipLaunchKernelGGL((gemm_nn_sub<T, 16>), dim3(tiles), dim3(kThreads), 0, stream, M, N, K, A, lda, B,
-                       ldb, C, ldc);
+    if (claim.ctr)
+        hipLaunchKernelGGL((gemm_nn_sub_x7<T, 16>), dim3(x7_grid(claim.cus, tiles)), dim3(kThreads), 0, stream, M, N,
+                           K, A, lda, B, ldb, C, ldc, claim.ctr, claim.next);
+    else
+        hipLaunchKernelGGL((gemm_nn_sub<T, 16>), dim3(tiles), dim3(kThreads), 0, stream, M, N, K, A, lda, B,
+                           ldb, C, ldc);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -460,17 +554,21 @@ int launch_syrk_lower(int M, int N, int K, const T* A, int lda, const T* B, int 
 
 template <typename H>
 int launch_gemm_half(int M, int N, int K, const H* Ah, int lda_h, const H* Bh, int ldb_h,
-                     const float* rs, const float* cs, float* C, int ldc, hipStream_t stream) {
+                     const float* rs, const float* cs, float* C, int ldc, hipStream_t stream, XcdClaim claim) {
     if (M <= 0 || N <= 0 || K <= 0) return 0;
     const int tiles = ((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
-    hipLaunchKernelGGL((gemm_half_sub<H>), dim3(tiles), dim3(kThreads), 0, stream, M, N, K, Ah, lda_h, Bh,
-                       ldb_h, rs, cs, C, ldc);
+    if (claim.ctr)
+        hipLaunchKernelGGL((gemm_half_sub_x7<H>), dim3(x7_grid(claim.cus, tiles)), dim3(kThreads), 0, stream, M, N, K,
+                           Ah, lda_h, Bh, ldb_h, rs, cs, C, ldc, claim.ctr, claim.next);
+    else
+        hipLaunchKernelGGL((gemm_half_sub<H>), dim3(tiles), dim3(kThreads), 0, stream, M, N, K, Ah, lda_h, Bh,
+                           ldb_h, rs, cs, C, ldc);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template int launch_gemm<double>(int, int, int, const double*, int, const double*, int, double*, int,
-                                 hipStream_t);
-template int launch_gemm<float>(int, int, int, const float*, int, const float*, int, float*, int, hipStream_t);
+                                 hipStream_t, XcdClaim);
+template int launch_gemm<float>(int, int, int, const float*, int, const float*, int, float*, int, hipStream_t, XcdClaim);
 template int launch_gemm_hh<double>(int, int, int, const double*, int, const double*, int, double*, int,
                                     hipStream_t);
 template int launch_gemm_split<double>(int, int, int, int, const double*, int, const double*, int, double*, int,
@@ -478,9 +576,9 @@ template int launch_gemm_split<double>(int, int, int, int, const double*, int, c
 template int launch_syrk_lower<double>(int, int, int, const double*, int, const double*, int, double*, int, int,
                                        hipStream_t);
 template int launch_gemm_half<_Float16>(int, int, int, const _Float16*, int, const _Float16*, int,
-                                        const float*, const float*, float*, int, hipStream_t);
+                                        const float*, const float*, float*, int, hipStream_t, XcdClaim);
 template int launch_gemm_half<__bf16>(int, int, int, const __bf16*, int, const __bf16*, int, const float*,
-                                      const float*, float*, int, hipStream_t);
+                                      const float*, float*, int, hipStream_t, XcdClaim);
 
 // One MFMA on lane-indexed values, to check the operand/result lane layout.
 __global__ void probe_mfma_f64_kernel(double* out) {

@@ -34,11 +34,14 @@ struct PanelArgs {
     unsigned tag_base;    // unique per launch: (launch number << 10); step d uses tag_base + d
     long long spin_limit; // barrier wait bound, wall-clock ticks
     int occupancy;        // register budget variant: 1 = whole register file, 2 = half
+    int one_xcd;          // 1: all work-groups on XCD 0 (the grid holds 8 per participant)
+    unsigned* rank;       // one_xcd: rank counter of the participants, 0 at launch
 };
 
 template <typename T>
 int launch_panel(const PanelArgs<T>& args, int wgs, hipStream_t stream);
 int panel_max_rows_per_wg();
+int launch_xcd_probe(int* out, int wgs, hipStream_t stream);
 int panel_threads();
 
 template <typename T, typename H>
@@ -54,6 +57,8 @@ struct SwapTrsmArgs {
     H* uh;                // optional half copy of U12: uh[col*lduh + t], t = row - r0
     long long lduh;
     float* cs;            // per-column inverse scales of uh, indexed by column
+    unsigned* claim;      // non-null: XCD 0 is left free and slabs are claimed from this counter
+    unsigned* claim_next; // (the counter of the next such launch on the stream, cleared by this one)
 };
 
 template <typename T, typename H>
@@ -63,8 +68,11 @@ int launch_swap_trsm(const SwapTrsmArgs<T, H>& args, hipStream_t stream);
 template <typename T>
 int launch_diag_inv(const T* A, long long lda, int r0, int w, T* linv, hipStream_t stream);
 // rows r0 .. r0+m-1 of columns [c0, c1): the interchanges of a panel of width w
+// claim non-null: XCD 0 is left free, column blocks claimed from *claim
+// (claim_next: the next such launch's counter, cleared here)
 template <typename T>
-int launch_lswap(T* A, long long lda, int r0, int w, int m, const int* moves, int c0, int c1, hipStream_t stream);
+int launch_lswap(T* A, long long lda, int r0, int w, int m, const int* moves, int c0, int c1, hipStream_t stream,
+                 unsigned* claim = nullptr, unsigned* claim_next = nullptr);
 int launch_moves(const int* ipiv_rel, int w, int m, int* moves, hipStream_t stream);
 int launch_chunk_moves(const int* ipiv, int n, int W, int* moves, hipStream_t stream);
 template <typename H>
@@ -75,8 +83,19 @@ template <typename H>
 int launch_cols_half(const float* B, long long ldb, int k, int n, H* Uh, long long ldh, float* cs,
                      hipStream_t stream);
 
+// Counters of a launch that leaves XCD 0 free for a panel running there: the
+// work-groups on XCD 0 return at once, the others claim tiles from per-XCD
+// chunks (8 counters, `next` = those of the next such launch on the stream,
+// cleared by this one); `cus` sizes the persistent grid.
+struct XcdClaim {
+    unsigned* ctr = nullptr;
+    unsigned* next = nullptr;
+    int cus = 0;
+};
+// claim.ctr null: one work-group per tile on every XCD.
 template <typename T>
-int launch_gemm(int M, int N, int K, const T* A, int lda, const T* B, int ldb, T* C, int ldc, hipStream_t stream);
+int launch_gemm(int M, int N, int K, const T* A, int lda, const T* B, int ldb, T* C, int ldc, hipStream_t stream,
+                XcdClaim claim = XcdClaim());
 // C -= A B for the Householder block updates (the trailing-update tile, its own kernel name)
 template <typename T>
 int launch_gemm_hh(int M, int N, int K, const T* A, int lda, const T* B, int ldb, T* C, int ldc, hipStream_t stream);
@@ -86,7 +105,7 @@ int launch_gemm_split(int M, int N, int K, int ks, const T* A, int lda, const T*
                       long long cstride, hipStream_t stream);
 template <typename H>
 int launch_gemm_half(int M, int N, int K, const H* Ah, int lda_h, const H* Bh, int ldb_h, const float* rs,
-                     const float* cs, float* C, int ldc, hipStream_t stream);
+                     const float* cs, float* C, int ldc, hipStream_t stream, XcdClaim claim = XcdClaim());
 int launch_probe_mfma_f64(double* out, hipStream_t stream);
 
 // Symmetric update C -= A B^T on C's lower triangle (element (i,j) when

@@ -48,13 +48,15 @@ template <> struct Wpv<float> { static constexpr int n = 1; };
 __device__ __forceinline__ unsigned long long tagged(unsigned tag, unsigned payload) {
     return ((unsigned long long)tag << 32) | payload;
 }
+template <int S>
 __device__ __forceinline__ void put_value(unsigned long long* dst, double v, unsigned tag) {
     const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    xstore(&dst[0], tagged(tag, (unsigned)(b >> 32)));
-    xstore(&dst[1], tagged(tag, (unsigned)b));
+    xstore_s<S>(&dst[0], tagged(tag, (unsigned)(b >> 32)));
+    xstore_s<S>(&dst[1], tagged(tag, (unsigned)b));
 }
+template <int S>
 __device__ __forceinline__ void put_value(unsigned long long* dst, float v, unsigned tag) {
-    xstore(&dst[0], tagged(tag, __float_as_uint(v)));
+    xstore_s<S>(&dst[0], tagged(tag, __float_as_uint(v)));
 }
 __device__ __forceinline__ double get_value(const unsigned* w, double*) {
     return __longlong_as_double((long long)(((unsigned long long)w[0] << 32) | w[1]));
@@ -156,7 +158,7 @@ __device__ __forceinline__ void compose_block_moves(const int* piv, int nbw, int
 // of the panel shares the strided row accesses.  Each thread loads the block's
 // top rows from their sources and the extra rows' sources before it stores
 // anything, so the column's moves read only old values.
-template <typename T, int NB>
+template <typename T, int NB, int S>
 __device__ __forceinline__ void block_swap_trsm(T* A, long long lda, int w, int cb, int nbw, int g, int P,
                                                 const int* bmv, const T (*L)[NB + 1]) {
     // source indices are clamped to written entries, so no load can use an
@@ -170,13 +172,13 @@ __device__ __forceinline__ void block_swap_trsm(T* A, long long lda, int w, int 
         T x[NB], e[NB];
 #pragma unroll
         for (int r = 0; r < NB; ++r) {
-            const T v = colp[tsrc[min(r, nbw - 1)]];
+            const T v = cload<S>(colp + tsrc[min(r, nbw - 1)]);
             x[r] = (r < nbw) ? v : T(0);
         }
 #pragma unroll
         for (int s = 0; s < NB; ++s) {
             e[s] = T(0);
-            if (s < ne) e[s] = colp[bmv[2 + 2 * min(s, em1)]];
+            if (s < ne) e[s] = cload<S>(colp + bmv[2 + 2 * min(s, em1)]);
         }
         if (col >= cb + nbw) {
             const T* Lf = &L[0][0];
@@ -188,10 +190,10 @@ __device__ __forceinline__ void block_swap_trsm(T* A, long long lda, int w, int 
         }
 #pragma unroll
         for (int r = 0; r < NB; ++r)
-            if (r < nbw) colp[cb + r] = x[r];
+            if (r < nbw) cstore<S>(colp + cb + r, x[r]);
 #pragma unroll
         for (int s = 0; s < NB; ++s)
-            if (s < ne) colp[bmv[1 + 2 * min(s, em1)]] = e[s];
+            if (s < ne) cstore<S>(colp + bmv[1 + 2 * min(s, em1)], e[s]);
     }
 }
 
@@ -203,7 +205,7 @@ __device__ __forceinline__ void block_swap_trsm(T* A, long long lda, int w, int 
 // L fragments come from the LDS copy of the finished columns (or from memory
 // when that copy does not fit), the U fragments from LDS (staged transposed,
 // zero past ncols), and each C tile is loaded, updated and stored once.
-template <typename T, int NB, int RPT>
+template <typename T, int NB, int RPT, int S>
 __device__ __forceinline__ void inpanel_update(T* A, long long lda, int g, int m, int cb, int nbw, int right0,
                                                int ncols, const T (*U)[NB],
                                                const T (*fin)[FinCfg<T, NB, RPT>::cols]) {
@@ -224,7 +226,7 @@ __device__ __forceinline__ void inpanel_update(T* A, long long lda, int g, int m
                 const int k = 4 * ks + lg;
                 T v;
                 if constexpr (FinCfg<T, NB, RPT>::lds) v = fin[k][loc];
-                else v = A[min(g * R + loc, m - 1) + (long long)(cb + k) * lda];
+                else v = cload<S>(A + min(g * R + loc, m - 1) + (long long)(cb + k) * lda);
                 lf[q][rb][ks] = (k < nbw) ? -v : T(0);
             }
         }
@@ -241,7 +243,7 @@ __device__ __forceinline__ void inpanel_update(T* A, long long lda, int g, int m
                 for (int r = 0; r < 4; ++r) {
                     const int cc = ct * 16 + Acc<T>::col(lg, r);
                     const bool ok = rok && cc < ncols;
-                    const T v = A[(ok ? row : right0) + (long long)(right0 + (ok ? cc : 0)) * lda];
+                    const T v = cload<S>(A + (ok ? row : right0) + (long long)(right0 + (ok ? cc : 0)) * lda);
                     c[q][rb][r] = ok ? v : T(0);
                 }
             }
@@ -270,7 +272,7 @@ __device__ __forceinline__ void inpanel_update(T* A, long long lda, int g, int m
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int c = ct * 16 + Acc<T>::col(lg, r);
-                    if (rok && c < ncols) A[row + (long long)(right0 + c) * lda] = cur[q][rb][r];
+                    if (rok && c < ncols) cstore<S>(A + row + (long long)(right0 + c) * lda, cur[q][rb][r]);
                 }
             }
     }
@@ -280,13 +282,33 @@ __device__ __forceinline__ void inpanel_update(T* A, long long lda, int g, int m
 // block column j+s of row row_of(q); finished columns go to memory (and to the
 // LDS copy `fin`) at once, so every register index is a compile-time constant
 // and the loop is not unrolled.
-template <typename T, int NB, int RPT, int OCC>
+//
+// Every access that other work-groups depend on is a relaxed atomic at agent
+// scope (see common.hpp).  ONE_XCD places the launch on XCD 0: the grid holds
+// 8 work-groups per participant, dealt round-robin to the 8 XCDs; the work-
+// groups that find themselves on XCD 0 (hardware register XCC_ID) take a rank
+// from a counter (cleared before the launch) and take part, the others return
+// at once.  Should fewer than P land there, the first wait runs out and the
+// launch reports a barrier time-out.  (Scoping the exchange to one XCD's L2
+// instead of the device coherence point was measured: workgroup-scope stores
+// and loads between CUs of one XCD did not always see each other.)
+template <typename T, int NB, int RPT, int OCC, bool ONE_XCD>
 __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
     typedef Xch<T, NB> X;
+    constexpr int S = __HIP_MEMORY_SCOPE_AGENT;
+    constexpr bool kOneXcd = ONE_XCD;
     __shared__ PanelShared<T, NB, RPT> sh;
+    __shared__ int s_rank;
     const int tid = threadIdx.x;
-    const int g = blockIdx.x;
-    const int P = gridDim.x;
+    const int P = kOneXcd ? (int)(gridDim.x >> 3) : (int)gridDim.x;
+    int g = (int)blockIdx.x;
+    if constexpr (kOneXcd) {
+        if (xcd_id() != 0) return;
+        if (tid == 0) s_rank = (int)__hip_atomic_fetch_add(a.rank, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        g = s_rank;
+        if (g >= P) return;
+    }
     const int R = kPanelThreads * RPT;
     const int m = a.m, w = a.w;
     const long long lda = a.lda;
@@ -294,7 +316,8 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
     unsigned epoch = 0;            // full-barrier count
 
     if (g == 0 && tid == 0 && a.sync_next) {
-        a.sync_next[0] = 0u;   // counter of the next launch's slot (its previous user has finished)
+        // counter of the next launch's slot (its previous user has finished)
+        xstore_s<__HIP_MEMORY_SCOPE_AGENT>(a.sync_next, 0u);
     }
     if (g == 0 && tid == 0 && a.moves) {
         // an empty interchange list until the composition at the end: a panel
@@ -307,7 +330,7 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
     // finished column t (< NB) of the current block, own row q
     auto fin_get = [&](int t, int q, int cb) -> T {
         if constexpr (FinCfg<T, NB, RPT>::lds) return sh.fin[t][q * kPanelThreads + tid];
-        else return A[min(row_of(q), m - 1) + (long long)(cb + t) * lda];
+        else return cload<S>(A + min(row_of(q), m - 1) + (long long)(cb + t) * lda);
     };
     auto fin_set = [&](int t, int q, T v) {
         if constexpr (FinCfg<T, NB, RPT>::lds) sh.fin[t][q * kPanelThreads + tid] = v;
@@ -315,7 +338,7 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
     // the same for the row of fin column `col` (= q * threads + owner thread)
     auto fin_at = [&](int t, int col, int cb) -> T {
         if constexpr (FinCfg<T, NB, RPT>::lds) return sh.fin[t][col];
-        else return A[min(g * R + col, m - 1) + (long long)(cb + t) * lda];
+        else return cload<S>(A + min(g * R + col, m - 1) + (long long)(cb + t) * lda);
     };
     auto fin_set_at = [&](int t, int col, T v) {
         if constexpr (FinCfg<T, NB, RPT>::lds) sh.fin[t][col] = v;
@@ -332,7 +355,7 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
             const T* rp = A + min(i, m - 1);        // clamped: unconditional loads, select below
 #pragma unroll
             for (int s = 0; s < NB; ++s) {
-                const T v = rp[(long long)(cb + min(s, nbw - 1)) * lda];
+                const T v = cload<S>(rp + (long long)(cb + min(s, nbw - 1)) * lda);
                 reg[q][s] = (i < m && s < nbw) ? v : T(0);
             }
         }
@@ -364,11 +387,11 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
             {
                 unsigned long long* slot = xa + (size_t)g * X::SW;
                 if (tid == 0) {
-                    xstore(&slot[0], tagged(tag, (unsigned)bi));
-                    put_value(&slot[1], bv, tag);
+                    xstore_s<S>(&slot[0], tagged(tag, (unsigned)bi));
+                    put_value<S>(&slot[1], bv, tag);
                 }
                 if (bi == 0x7fffffff && tid < NB)      // no candidate here: a zero row completes the slot
-                    put_value(&slot[1 + X::WPV + tid * X::WPV], T(0), tag);
+                    put_value<S>(&slot[1 + X::WPV + tid * X::WPV], T(0), tag);
 #pragma unroll
                 for (int q = 0; q < RPT; ++q) {
                     const int i = row_of(q);
@@ -386,7 +409,7 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
                             }
                             unsigned long long* dst = which == 0 ? slot + 1 + X::WPV
                                                                  : xa + (size_t)kMaxPanelWgs * X::SW;
-                            if (lane < NB) put_value(&dst[lane * X::WPV], v, tag);
+                            if (lane < NB) put_value<S>(&dst[lane * X::WPV], v, tag);
                         }
                     }
                 }
@@ -417,9 +440,9 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
                 while (pending) {
                     unsigned long long wv[MAXW];
 #pragma unroll
-                    for (int k = 0; k < MAXW; ++k) wv[k] = ((pending >> k) & 1u) ? xload(xa + off[k]) : 0ull;
+                    for (int k = 0; k < MAXW; ++k) wv[k] = ((pending >> k) & 1u) ? xload_s<S>(xa + off[k]) : 0ull;
                     unsigned errw = 0;
-                    if (tid == 0) errw = xload(a.sync + 1);
+                    if (tid == 0) errw = xload_s<__HIP_MEMORY_SCOPE_AGENT>(a.sync + 1);
 #pragma unroll
                     for (int k = 0; k < MAXW; ++k) {
                         if (((pending >> k) & 1u) && (unsigned)(wv[k] >> 32) == tag) {
@@ -434,7 +457,7 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
                 failed = (st & 2) != 0;
             }
             if (failed) {
-                if (tid == 0) xstore(a.sync + 1, 1u);
+                if (tid == 0) xstore_s<__HIP_MEMORY_SCOPE_AGENT>(a.sync + 1, 1u);
                 return;
             }
             // 4. global winner, computed by every wave from the headers (same
@@ -488,7 +511,7 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
                             const int row = g * R + col;
                             if (lane < nbw) {
                                 const T v = which == 0 ? drow_at(lane) : prow_at(lane);
-                                A[row + (long long)(cb + lane) * lda] = v;
+                                cstore<S>(A + row + (long long)(cb + lane) * lda, v);
                                 if (lane < j) fin_set_at(lane, col, v);
                             }
                             if (lane == ol) {
@@ -520,7 +543,7 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
 #pragma unroll
                     for (int s = 1; s < NB; ++s) reg[q][s] = reg[q][s] - l * pr[s];
                 }
-                if (i < m) A[i + (long long)d * lda] = reg[q][0];
+                if (i < m) cstore<S>(A + i + (long long)d * lda, reg[q][0]);
                 fin_set(j, q, reg[q][0]);
 #pragma unroll
                 for (int s = 0; s + 1 < NB; ++s) reg[q][s] = reg[q][s + 1];
@@ -535,9 +558,9 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
             // every work-group: the block's moves (from its own copy of the
             // pivots) and its share of the columns
             __syncthreads();           // the last step's pivot and block row are in LDS
-            // every work-group's rows as its last in-panel update left them (that
-            // update preceded its exchange words, which this work-group has read)
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            // every work-group's rows as its last in-panel update left them: that
+            // update completed before its exchange words of this block, which this
+            // work-group has read, and the loads below go to the coherence point
             // sh.L rows 0..nbw-1 hold the finished block rows (captured during the
             // column steps); rows past a ragged block's width are cleared
             if (nbw < NB) {
@@ -548,23 +571,23 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
             }
             if (tid < kWave) compose_block_moves<NB>(sh.piv + cb, nbw, cb, sh.bmv, sh.slot_row, sh.content);
             __syncthreads();
-            block_swap_trsm<T, NB>(A, lda, w, cb, nbw, g, P, sh.bmv, sh.L);
-            if (grid_barrier(a.sync, a.sync + 1, ++epoch, a.spin_limit)) return;
+            block_swap_trsm<T, NB, S>(A, lda, w, cb, nbw, g, P, sh.bmv, sh.L);
+            if (grid_barrier_nofence(a.sync, a.sync + 1, ++epoch, a.spin_limit, P)) return;
             // in-panel trailing update of my rows below the block: A[i, right] -= L[i, blk] U[blk, right]
             const int right0 = cb + nbw;
             const int ncols = w - right0;
             if (ncols > 0) {
                 for (int e = tid; e < NB * ncols; e += kPanelThreads) {
                     const int s = e % NB, cc = e / NB;
-                    sh.U[cc][s] = (s < nbw) ? A[(cb + s) + (long long)(right0 + cc) * lda] : T(0);
+                    sh.U[cc][s] = (s < nbw) ? cload<S>(A + (cb + s) + (long long)(right0 + cc) * lda) : T(0);
                 }
                 __syncthreads();
                 // every row of this work-group lies above right0: nothing to update
-                if (g * R + R > right0) inpanel_update<T, NB, RPT>(A, lda, g, m, cb, nbw, right0, ncols, sh.U, sh.fin);
+                if (g * R + R > right0) inpanel_update<T, NB, RPT, S>(A, lda, g, m, cb, nbw, right0, ncols, sh.U, sh.fin);
+                // the next block step of other work-groups reads these rows: they are
+                // complete before this work-group's first exchange word of the next block
+                wave_mem_drain();
                 __syncthreads();
-                // the next block step of other work-groups reads these rows: publish
-                // them before this work-group's first exchange word of the next block
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             }
         }
     }
@@ -586,10 +609,29 @@ int launch_panel(const PanelArgs<T>& args, int wgs, hipStream_t stream) {
     if (rpt < 1) rpt = 1;
     if (rpt > 4) return -1;   // caller must raise wgs
     dim3 block(kPanelThreads);
-    if (rpt == 1) hipLaunchKernelGGL((panel_kernel<T, NB, 1, 1>), dim3(wgs), block, 0, stream, args);
-    else if (rpt == 2) hipLaunchKernelGGL((panel_kernel<T, NB, 2, 1>), dim3(wgs), block, 0, stream, args);
-    else if (rpt <= 4) hipLaunchKernelGGL((panel_kernel<T, NB, 4, 1>), dim3(wgs), block, 0, stream, args);
+    if (args.one_xcd) {
+        const dim3 grid(8 * wgs);
+        if (rpt == 1) hipLaunchKernelGGL((panel_kernel<T, NB, 1, 1, true>), grid, block, 0, stream, args);
+        else if (rpt == 2) hipLaunchKernelGGL((panel_kernel<T, NB, 2, 1, true>), grid, block, 0, stream, args);
+        else hipLaunchKernelGGL((panel_kernel<T, NB, 4, 1, true>), grid, block, 0, stream, args);
+    } else {
+        if (rpt == 1) hipLaunchKernelGGL((panel_kernel<T, NB, 1, 1, false>), dim3(wgs), block, 0, stream, args);
+        else if (rpt == 2) hipLaunchKernelGGL((panel_kernel<T, NB, 2, 1, false>), dim3(wgs), block, 0, stream, args);
+        else hipLaunchKernelGGL((panel_kernel<T, NB, 4, 1, false>), dim3(wgs), block, 0, stream, args);
+    }
     return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// XCD of each of `wgs` work-groups (out[b] for work-group b): the host checks
+// the round-robin deal (work-group b on XCD b % 8) that the one-XCD panel
+// placement relies on.
+__global__ void xcd_probe_kernel(int* out) {
+    if (threadIdx.x == 0) out[blockIdx.x] = xcd_id();
+}
+
+int launch_xcd_probe(int* out, int wgs, hipStream_t stream) {
+    hipLaunchKernelGGL(xcd_probe_kernel, dim3(wgs), dim3(64), 0, stream, out);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int panel_max_rows_per_wg() { return kPanelThreads * 4; }

@@ -30,6 +30,11 @@ struct DeviceState {
     long long spin_limit = 0;          // ~2 s of the device wall clock
     int panel_occupancy = 1;           // panel kernel register budget variant (LU_PANEL_OCC)
     int wide_rows = 20480;             // FP64 panels taller than this use 1024 rows per group (LU_WIDE_ROWS)
+    int xcd_round_robin = 0;           // 1: work-group b of a launch runs on XCD b % 8 (probed at set-up)
+    int panel_one_xcd = 0;             // LU panels on XCD 0 when they fit its CUs (LU_PANEL_XCD)
+    int island = 0;                    // look-ahead with XCD 0 kept for the panels (LU_ISLAND)
+    Buffer claims;                     // work counters of the XCD-0-free launches (update stream)
+    int claim_par[3] = {0, 0, 0};      // ping-pong parity: GEMM, swap+TRSM, left swaps
     hipStream_t update_stream = nullptr;  // the bulk trailing update
     hipStream_t panel_stream = nullptr;
     hipStream_t swap_stream = nullptr;   // interchanges of finished columns (off the critical path)

@@ -15,6 +15,8 @@
 //   3. U12 goes back to the matrix (and, in the mixed-precision mode, to a
 //      half-precision copy with one power-of-two scale per column).
 // lswap_kernel: the same interchanges on finished columns left of the panel.
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "mfma.hpp"
@@ -73,7 +75,7 @@ __global__ __launch_bounds__(64) void diag_inv_kernel(const T* __restrict__ A, l
 // ROWT row tiles (16 rows each) per wave, NCT column tiles (16 columns) per
 // work-group; wave v owns row tiles v, v+4, v+8, ...
 template <typename T, typename H, int ROWT, int NCT>
-__global__ __launch_bounds__(kThreads, 2) void swap_trsm_kernel(SwapTrsmArgs<T, H> a) {
+__device__ __forceinline__ void swap_trsm_slab(const SwapTrsmArgs<T, H>& a, int slab) {
     typedef typename Acc<T>::type V4;
     constexpr int BN = 16 * NCT;
     constexpr int LDX = BN + 1;
@@ -90,7 +92,8 @@ __global__ __launch_bounds__(kThreads, 2) void swap_trsm_kernel(SwapTrsmArgs<T, 
     const int l16 = lane % 16, lg = lane / 16;
     const int w = a.w;
     const int nrt = (w + 15) / 16;
-    const int c_base = a.c0 + blockIdx.x * BN;
+    const int c_base = a.c0 + slab * BN;
+    if (c_base >= a.c1) return;
     const long long lda = a.lda;
     T* __restrict__ Atop = a.A + a.r0;                  // row r0 of column 0
     const T* __restrict__ L = a.A + a.r0 + (long long)a.r0 * lda;   // L11 at (r0, r0)
@@ -298,13 +301,41 @@ __global__ __launch_bounds__(kThreads, 2) void swap_trsm_kernel(SwapTrsmArgs<T, 
     }
 }
 
+// One slab per work-group, or -- beside a panel that holds XCD 0 -- the
+// work-groups on XCD 0 return at once and the others claim slabs from a
+// counter until none is left (a counter of the launch before, which has
+// finished on this stream, is cleared here for the next launch).
+template <typename T, typename H, int ROWT, int NCT>
+__global__ __launch_bounds__(kThreads, 2) void swap_trsm_kernel(SwapTrsmArgs<T, H> a) {
+    constexpr int BN = 16 * NCT;
+    if (!a.claim) {
+        swap_trsm_slab<T, H, ROWT, NCT>(a, blockIdx.x);
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) xstore(a.claim_next, 0u);
+    if (xcd_id() == 0) return;
+    const int nslabs = (a.c1 - a.c0 + BN - 1) / BN;
+    __shared__ int s_slab;
+    for (;;) {
+        __syncthreads();                 // the previous slab's shared-memory reads are done
+        if (threadIdx.x == 0) s_slab = (int)atomicAdd(a.claim, 1u);
+        __syncthreads();
+        const int slab = s_slab;
+        if (slab >= nslabs) break;
+        swap_trsm_slab<T, H, ROWT, NCT>(a, slab);
+    }
+}
+
 // Interchanges only, on columns [c0, c1): all reads of a column before its writes.
 // The list is read as in swap_trsm_kernel (rows relative to r0, m rows from there).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void lswap_kernel(T* A, long long lda, int r0, int w, int m, const int* moves,
-                                                         int c0, int c1, int cols_per_wg) {
+                                                         int c0, int c1, int cols_per_wg, unsigned* claim,
+                                                         unsigned* claim_next) {
     __shared__ int mv[2 * 2 * kMovesMaxW];   // (dst, src) pairs, top then extra
     const int tid = threadIdx.x;
+    if (claim && blockIdx.x == 0 && threadIdx.x == 0) xstore(claim_next, 0u);
+    if (claim && xcd_id() == 0) return;      // XCD 0 is left to the panel
     __shared__ int cnt_s;
     if (tid == 0) cnt_s = 0;
     __syncthreads();
@@ -328,8 +359,21 @@ __global__ __launch_bounds__(kThreads) void lswap_kernel(T* A, long long lda, in
     __syncthreads();
     const int cnt = cnt_s;
     constexpr int kPer = (2 * kMovesMaxW + kThreads - 1) / kThreads;
-    const int cb = c0 + blockIdx.x * cols_per_wg;
-    for (int c = cb; c < min(c1, cb + cols_per_wg); ++c) {
+    __shared__ int s_blk;
+    const int nblk = (c1 - c0 + cols_per_wg - 1) / cols_per_wg;
+    for (int it = 0;; ++it) {
+      int blk;
+      if (claim) {                              // blocks of columns claimed from a counter
+          __syncthreads();
+          if (tid == 0) s_blk = (int)atomicAdd(claim, 1u);
+          __syncthreads();
+          blk = s_blk;
+      } else {
+          blk = it == 0 ? (int)blockIdx.x : nblk;
+      }
+      if (blk >= nblk) break;
+      const int cb = c0 + blk * cols_per_wg;
+      for (int c = cb; c < min(c1, cb + cols_per_wg); ++c) {
         T* col = A + r0 + (long long)c * lda;
         T v[kPer];
 #pragma unroll
@@ -344,6 +388,7 @@ __global__ __launch_bounds__(kThreads) void lswap_kernel(T* A, long long lda, in
             if (s < cnt) col[mv[2 * s]] = v[u];
         }
         __syncthreads();
+      }
     }
 }
 
@@ -443,7 +488,10 @@ int launch_swap_trsm(const SwapTrsmArgs<T, H>& args, hipStream_t stream) {
     const int nrt = (args.w + 15) / 16;
     const int ncols = args.c1 - args.c0;
     auto go = [&](auto kern, int bn) {
-        hipLaunchKernelGGL(kern, dim3((ncols + bn - 1) / bn), dim3(kThreads), 0, stream, args);
+        const int slabs = (ncols + bn - 1) / bn;
+        // claimed slabs: about as many work-groups as slabs, at most two per CU
+        const int grid = args.claim ? std::min(slabs + slabs / 7 + 8, 512) : slabs;
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, stream, args);
     };
     if (nrt <= 4) go(swap_trsm_kernel<T, H, 1, 4>, 64);
     else if (nrt <= 8) go(swap_trsm_kernel<T, H, 2, 4>, 64);
@@ -467,13 +515,15 @@ template int launch_diag_inv<double>(const double*, long long, int, int, double*
 template int launch_diag_inv<float>(const float*, long long, int, int, float*, hipStream_t);
 
 template <typename T>
-int launch_lswap(T* A, long long lda, int r0, int w, int m, const int* moves, int c0, int c1, hipStream_t stream) {
+int launch_lswap(T* A, long long lda, int r0, int w, int m, const int* moves, int c0, int c1, hipStream_t stream,
+                 unsigned* claim, unsigned* claim_next) {
     if (c1 <= c0 || m <= 0) return 0;
     if (w < 1 || w > kMovesMaxW) return -1;
     const int per = 4;
-    const int grid = (c1 - c0 + per - 1) / per;
+    const int blocks = (c1 - c0 + per - 1) / per;
+    const int grid = claim ? std::min(blocks + blocks / 7 + 8, 1024) : blocks;
     hipLaunchKernelGGL((lswap_kernel<T>), dim3(grid), dim3(kThreads), 0, stream, A, lda, r0, w, m, moves, c0, c1,
-                       per);
+                       per, claim, claim_next);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -503,8 +553,10 @@ int launch_l21_half(const float* A, long long lda, int m, int w, H* Lh, long lon
 template int launch_swap_trsm<double, _Float16>(const SwapTrsmArgs<double, _Float16>&, hipStream_t);
 template int launch_swap_trsm<float, _Float16>(const SwapTrsmArgs<float, _Float16>&, hipStream_t);
 template int launch_swap_trsm<float, __bf16>(const SwapTrsmArgs<float, __bf16>&, hipStream_t);
-template int launch_lswap<double>(double*, long long, int, int, int, const int*, int, int, hipStream_t);
-template int launch_lswap<float>(float*, long long, int, int, int, const int*, int, int, hipStream_t);
+template int launch_lswap<double>(double*, long long, int, int, int, const int*, int, int, hipStream_t, unsigned*,
+                                  unsigned*);
+template int launch_lswap<float>(float*, long long, int, int, int, const int*, int, int, hipStream_t, unsigned*,
+                                 unsigned*);
 template int launch_l21_half<_Float16>(const float*, long long, int, int, _Float16*, long long, float*,
                                        hipStream_t);
 template int launch_l21_half<__bf16>(const float*, long long, int, int, __bf16*, long long, float*, hipStream_t);

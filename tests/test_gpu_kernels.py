@@ -193,3 +193,21 @@ def test_wide_fp64_panel_matches_oracle(gpu, tmp_path, m, w):
         if ipiv[t] != t:
             got[[t, ipiv[t]], :] = got[[ipiv[t], t], :]
     assert np.abs(got - LU[:, :w]).max() <= 1e-12 * max(1.0, np.abs(LU[:, :w]).max())
+
+
+def test_xcd_probe_round_robin(gpu):
+    """The XCD-island schedule keeps the panels on XCD 0 by relying on the
+    round-robin deal of work-groups to the 8 XCDs (work-group b on XCD
+    (b + c) % 8 for an offset c of the launch).  The probe reads the XCC_ID
+    register of 64 work-groups; the library's verdict must match what it
+    read, and on an MI355X in its single-partition mode the deal holds."""
+    import numpy as np
+    import torch
+    out = np.full(64, -1, dtype=np.int32)
+    rc = gpu.load().lu_k_xcd_probe(out.ctypes.data)
+    assert rc in (0, 1), rc
+    assert np.all((out >= 0) & (out < 8))
+    rr = bool(np.all((out - out[0] - np.arange(64)) % 8 == 0))
+    assert rc == int(rr), out.tolist()
+    if torch.cuda.get_device_properties(0).multi_processor_count == 256:
+        assert rr, out.tolist()
