@@ -13,6 +13,11 @@
  *                   (A22 -= A21 A12) (Sec. 3.4, 3.5)
  *   LSWAP(k,0,s_k)  apply the interchanges of panel k to the finished
  *                   columns left of it (the left half of laswp, Sec. 3.4)
+ *   LPERM(N-1,0,s_N-1) the same for every panel at once, deferred to the end:
+ *                   the columns of each panel k take the interchanges of all
+ *                   later panels (rows >= s_k+1) in one permutation per
+ *                   column.  Nothing reads those columns again before the
+ *                   end, so the result equals that of the LSWAP tasks.
  * A schedule places these tasks in a program order that is a valid
  * sequential order of the algorithm (Listing 3 for depth 0, Listing 5 of
  * Sec. 4 for depth 1, two panels ahead for depth 2) and assigns each to one
@@ -35,6 +40,7 @@ extern "C" {
 #define LU_TASK_PANEL  0
 #define LU_TASK_UPDATE 1
 #define LU_TASK_LSWAP  2
+#define LU_TASK_LPERM  3
 
 #define LU_PLAN_STREAMS  3
 #define LU_PLAN_MAX_WAIT 2   /* = LU_PLAN_STREAMS - 1 */
@@ -76,7 +82,10 @@ int lu_plan_build_panels(int n, const int* starts, int npanels, int depth, lu_pl
 
 /* As lu_plan_build_panels; interchanges = 0 gives the task list of the
  * factorizations without row interchanges (Cholesky, QR: no LU_TASK_LSWAP
- * tasks and no waits on pivots), interchanges != 0 the LU's.  Same returns. */
+ * tasks and no waits on pivots), 1 the LU's with one LU_TASK_LSWAP per
+ * step (as lu_plan_build_panels), 2 the LU's with the left interchanges
+ * deferred to one final LU_TASK_LPERM task (on stream 0).  Same returns, and
+ * -6 for another value of interchanges. */
 int lu_plan_build_panels_ex(int n, const int* starts, int npanels, int depth, int interchanges,
                             lu_plan_task_t* out, int max_tasks);
 

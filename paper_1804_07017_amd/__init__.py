@@ -22,7 +22,7 @@ LU_FP64, LU_FP32, LU_MIXED_FP16, LU_MIXED_BF16 = 0, 1, 2, 3
 LU_ERR_HIP, LU_ERR_BARRIER, LU_ERR_NOMEM, LU_ERR_UNSUPPORTED, LU_ERR_NONFINITE = -100, -101, -102, -103, -104
 LU_ERR_SINGULAR = -105
 LU_IR_OK, LU_IR_FELL_BACK, LU_IR_RESID_HIGH = 0, 1, 2
-LU_TASK_PANEL, LU_TASK_UPDATE, LU_TASK_LSWAP = 0, 1, 2
+LU_TASK_PANEL, LU_TASK_UPDATE, LU_TASK_LSWAP, LU_TASK_LPERM = 0, 1, 2, 3
 SELECTOR_PARAMS = 490
 
 _lib = None
@@ -349,7 +349,8 @@ def lu_plan_build_panels(n, starts, depth, max_tasks=None):
 
 def lu_plan_build_panels_ex(n, starts, depth, interchanges, max_tasks=None):
     """Task list for explicit panel boundaries, with or without the LU's
-    interchange tasks (host only). Returns (rc, list of dicts)."""
+    interchange tasks (interchanges: 0 none, 1 one LSWAP per step, 2 one
+    deferred LPERM at the end; host only). Returns (rc, list of dicts)."""
     N = max(0, len(starts) - 1)
     if max_tasks is None:
         max_tasks = 8 * N + 16

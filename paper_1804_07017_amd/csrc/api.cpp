@@ -200,7 +200,7 @@ void release_all() {
         if (s->swap_stream) hipStreamDestroy(s->swap_stream);
         if (s->sync) hipFree(s->sync);
         if (s->info) hipFree(s->info);
-        Buffer* bufs[] = {&s->claims, &s->cand, &s->moves, &s->linv, &s->lh, &s->uh, &s->rs, &s->cs, &s->solve_moves, &s->flags,
+        Buffer* bufs[] = {&s->plan_starts, &s->claims, &s->cand, &s->moves, &s->linv, &s->lh, &s->uh, &s->rs, &s->cs, &s->solve_moves, &s->flags,
                           &s->partial, &s->ir_r, &s->ir_x32, &s->ir_a32, &s->ir_a64, &s->ir_norms, &s->ir_ipiv,
                           &s->ir_b, &s->qr_v, &s->qr_vt, &s->qr_t, &s->qr_tt, &s->qr_w, &s->qr_ws, &s->qr_ym, &s->qr_part,
                           &s->band_z, &s->band_v, &s->band_vt, &s->band_t, &s->band_tt, &s->band_w,
@@ -272,7 +272,10 @@ const DeviceState::Plan* get_plan(DeviceState* s, int n, const lu_schedule_t& sc
     if (s->plans.size() > 64) s->plans.clear();
     DeviceState::Plan p;
     p.starts = panel_starts(n, sch.b, taper, prec_class(prec));
-    if (build_plan(n, p.starts, sch.depth, p.tasks) < 0) return nullptr;
+    // left interchanges deferred to one final permutation when a column
+    // segment fits the permutation kernel, else one LSWAP task per step
+    const int swaps = (p.starts.size() >= 3 && n - p.starts[1] <= kLpermMaxRows) ? 2 : 1;
+    if (build_plan(n, p.starts, sch.depth, p.tasks, swaps) < 0) return nullptr;
     return &(s->plans[key] = std::move(p));
 }
 
@@ -445,6 +448,11 @@ int execute(DeviceState* s, int n, T* A, long long lda, int* ipiv, int* info, co
                     if (stop) LU_HIP(hipEventRecord(stop, st));
                 }
             }
+        } else if (t.kind == kTaskLperm) {
+            if ((rc = ensure(s->plan_starts, (N + 1) * sizeof(int)))) return rc;
+            int* dst = reinterpret_cast<int*>(s->plan_starts.ptr);
+            LU_HIP(hipMemcpyAsync(dst, starts.data(), (N + 1) * sizeof(int), hipMemcpyHostToDevice, st));
+            if (launch_lperm<T>(A, lda, n, N, starts.data(), dst, moves, st)) return LU_ERR_HIP;
         } else {
             unsigned* nx = nullptr;
             unsigned* cl = island ? one_claim(2, &nx) : nullptr;

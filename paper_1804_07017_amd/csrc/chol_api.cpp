@@ -25,7 +25,7 @@ int chol_execute(DeviceState* s, int n, double* A, long long lda, int* info, int
     starts.push_back(n);
     const int N = (int)starts.size() - 1;
     std::vector<PlanTask> plan;
-    if (build_plan(n, starts, depth, plan, false) < 0) return LU_ERR_UNSUPPORTED;
+    if (build_plan(n, starts, depth, plan, 0) < 0) return LU_ERR_UNSUPPORTED;
     int rc;
     size_t nrec = 0;
     for (const PlanTask& t : plan) nrec += t.record ? 1 : 0;

@@ -74,6 +74,16 @@ template <typename T>
 int launch_lswap(T* A, long long lda, int r0, int w, int m, const int* moves, int c0, int c1, hipStream_t stream,
                  unsigned* claim = nullptr, unsigned* claim_next = nullptr);
 int launch_moves(const int* ipiv_rel, int w, int m, int* moves, hipStream_t stream);
+// Deferred left interchanges (update.hip, lperm_kernel): every panel k < N-1
+// of the factorization takes the interchanges of all later panels; moves of
+// panel j at moves + j*kMovesLen; starts on the host and on the device
+// (N+1 ints).  Needs n - starts[1] <= kLpermMaxRows.
+constexpr int kLpermThreads = 1024;
+constexpr int kLpermCols = 32;          // columns per work-group
+constexpr int kLpermMaxRows = 32768;    // rows of a column segment (32 per thread; the LDS holds one int per row)
+template <typename T>
+int launch_lperm(T* A, long long lda, int n, int N, const int* starts_host, const int* starts_dev, const int* moves,
+                 hipStream_t stream);
 int launch_chunk_moves(const int* ipiv, int n, int W, int* moves, hipStream_t stream);
 template <typename H>
 int launch_l21_half(const float* A, long long lda, int m, int w, H* Lh, long long ldh, float* rs,

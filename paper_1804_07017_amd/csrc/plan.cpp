@@ -21,7 +21,7 @@ struct Access {
     int w0, w1;      // columns written
     int r0, r1;      // columns read (besides the written ones)
     int ipiv_w;      // pivot block written (-1 none)
-    int ipiv_r;      // pivot block read (-1 none)
+    int ipiv_r;      // pivot block read (-1 none, -2 every block)
 };
 
 inline bool overlap(int a0, int a1, int b0, int b1) { return a0 < b1 && b0 < a1 && a0 < a1 && b0 < b1; }
@@ -40,6 +40,9 @@ Access access_of(const PlanTask& t, const std::vector<int>& starts) {
     case kTaskLswap:
         a.ipiv_r = t.step;
         break;
+    case kTaskLperm:
+        a.ipiv_r = -2;
+        break;
     }
     return a;
 }
@@ -49,8 +52,8 @@ bool conflicts(const Access& e, const Access& l) {
     if (overlap(e.w0, e.w1, l.w0, l.w1)) return true;   // WAW
     if (overlap(e.w0, e.w1, l.r0, l.r1)) return true;   // RAW
     if (overlap(e.r0, e.r1, l.w0, l.w1)) return true;   // WAR
-    if (e.ipiv_w >= 0 && (e.ipiv_w == l.ipiv_r || e.ipiv_w == l.ipiv_w)) return true;
-    if (l.ipiv_w >= 0 && e.ipiv_r == l.ipiv_w) return true;
+    if (e.ipiv_w >= 0 && (e.ipiv_w == l.ipiv_r || l.ipiv_r == -2 || e.ipiv_w == l.ipiv_w)) return true;
+    if (l.ipiv_w >= 0 && (e.ipiv_r == l.ipiv_w || e.ipiv_r == -2)) return true;
     return false;
 }
 
@@ -88,7 +91,8 @@ int build_plan(int n, int b, int depth, std::vector<PlanTask>& out) {
     return build_plan(n, panel_starts(n, b, 0, 0), depth, out);
 }
 
-int build_plan(int n, const std::vector<int>& starts, int depth, std::vector<PlanTask>& out, bool lswap) {
+int build_plan(int n, const std::vector<int>& starts, int depth, std::vector<PlanTask>& out, int swaps) {
+    const bool lswap = swaps == 1;
     out.clear();
     if (n < 0) return -1;
     if (depth < 0 || depth > 2) return -3;
@@ -136,6 +140,8 @@ int build_plan(int n, const std::vector<int>& starts, int depth, std::vector<Pla
             if (k >= 1 && lswap) push(kTaskLswap, k, 0, starts[k], 2);
         }
     }
+    // deferred left interchanges: one task after everything else, on the update stream
+    if (swaps == 2 && N >= 2) push(kTaskLperm, N - 1, 0, starts[N - 1], 0);
     // Derive cross-stream waits from data accesses.
     const int T = (int)out.size();
     std::vector<Access> acc(T);
@@ -207,8 +213,9 @@ extern "C" int lu_plan_build_panels_ex(int n, const int* starts, int npanels, in
     if (n > 0 && (!starts || npanels < 1)) return -4;
     std::vector<int> st;
     if (n > 0) st.assign(starts, starts + npanels + 1);
+    if (interchanges < 0 || interchanges > 2) return -6;
     std::vector<lu::PlanTask> v;
-    int r = lu::build_plan(n, st, depth, v, interchanges != 0);
+    int r = lu::build_plan(n, st, depth, v, interchanges);
     if (r < 0) return r;
     return export_plan(v, out, max_tasks);
 }

@@ -6,7 +6,7 @@
 
 namespace lu {
 
-enum { kTaskPanel = LU_TASK_PANEL, kTaskUpdate = LU_TASK_UPDATE, kTaskLswap = LU_TASK_LSWAP };
+enum { kTaskPanel = LU_TASK_PANEL, kTaskUpdate = LU_TASK_UPDATE, kTaskLswap = LU_TASK_LSWAP, kTaskLperm = LU_TASK_LPERM };
 constexpr int kPlanStreams = LU_PLAN_STREAMS;
 
 struct PlanTask {
@@ -23,7 +23,8 @@ std::vector<int> panel_starts(int n, int b, int taper, int prec);
 int taper_width(int prec, int trailing);
 
 int build_plan(int n, int b, int depth, std::vector<PlanTask>& out);
-// lswap = false: no LSWAP tasks (a factorization without row interchanges)
-int build_plan(int n, const std::vector<int>& starts, int depth, std::vector<PlanTask>& out, bool lswap = true);
+// swaps: 0 no left interchanges (a factorization without row interchanges),
+// 1 one LSWAP task per step, 2 one LPERM task at the end
+int build_plan(int n, const std::vector<int>& starts, int depth, std::vector<PlanTask>& out, int swaps = 1);
 
 }  // namespace lu

@@ -33,7 +33,7 @@ int qr_execute(DeviceState* s, int m, int n, double* A, long long lda, double* t
     starts.push_back(n);
     const int N = (int)starts.size() - 1;
     std::vector<PlanTask> plan;
-    if (build_plan(n, starts, depth, plan, false) < 0) return LU_ERR_UNSUPPORTED;
+    if (build_plan(n, starts, depth, plan, 0) < 0) return LU_ERR_UNSUPPORTED;
     int rc;
     const size_t vwords = (size_t)m * b;
     if ((rc = ensure(s->qr_v, kQrSlots * vwords * sizeof(double)))) return rc;

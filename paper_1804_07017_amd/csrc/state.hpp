@@ -47,6 +47,7 @@ struct DeviceState {
     unsigned panel_launches = 0;       // numbers the panel launches (exchange tags)
     Buffer cand;                       // candidate exchange area of the panel kernel
     Buffer moves;                      // per-panel composed interchanges
+    Buffer plan_starts;                // panel boundaries of the running plan (deferred left interchanges)
     Buffer linv;                       // per-panel inverses of the 16x16 diagonal L blocks
     int* info = nullptr;               // library INFO word
     hipStream_t last_stream = nullptr; // stream of the last factorization

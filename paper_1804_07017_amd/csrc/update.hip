@@ -392,6 +392,72 @@ __global__ __launch_bounds__(kThreads) void lswap_kernel(T* A, long long lda, in
     }
 }
 
+// Left interchanges deferred to the end of the factorization (the LPERM task):
+// the columns of panel k take the interchanges of every later panel j > k, on
+// rows >= r0 = starts[k+1], as one permutation sigma_k of those rows, where
+// applying panels k+1, k+2, ... in order to a column gives new[r] =
+// old[sigma_k(r)].  With M_j the permutation of panel j's composed moves
+// (new[dst] = old[src]), sigma_k = M_{k+1} o sigma_{k+1} and so
+// sigma_k^-1 = sigma_{k+1}^-1 o M_{k+1}^-1: starting from the identity and
+// taking the panels from the last one down to k+1, each panel's moves set
+// inv[src] = inv[dst] (all reads before the writes).  Then every column
+// segment is read whole into registers and written back permuted,
+// new[inv[i]] = old[i].  Work-group b takes kLpermCols columns of one panel
+// (panels in order, ceil(w_k / kLpermCols) work-groups each) and rebuilds
+// that panel's inv in LDS.  The moves are read defensively (moves.hpp).
+template <typename T>
+__global__ __launch_bounds__(kLpermThreads) void lperm_kernel(T* A, long long lda, int n, int N,
+                                                             const int* __restrict__ starts,
+                                                             const int* __restrict__ moves) {
+    extern __shared__ int inv[];
+    const int tid = threadIdx.x;
+    int b = blockIdx.x, k = 0;
+    for (; k < N - 1; ++k) {
+        const int nb = (starts[k + 1] - starts[k] + kLpermCols - 1) / kLpermCols;
+        if (b < nb) break;
+        b -= nb;
+    }
+    if (k >= N - 1) return;
+    const int r0 = starts[k + 1], L = n - r0;
+    const int c0 = starts[k] + b * kLpermCols, c1 = min(starts[k + 1], c0 + kLpermCols);
+    for (int i = tid; i < L; i += kLpermThreads) inv[i] = i;
+    __syncthreads();
+    for (int j = N - 1; j > k; --j) {
+        const int* mv = moves + (size_t)j * kMovesLen;
+        const int wj = starts[j + 1] - starts[j], mj = n - starts[j], o = starts[j] - r0;
+        const int nt = moves_top_count(mv, wj), ne = moves_extra_count(mv, wj);
+        int d = -1, src = 0, val = 0;
+        if (tid < nt) {
+            int dd, ss;
+            if (moves_top(mv, tid, wj, mj, dd, ss)) { d = dd + o; src = ss + o; }
+        } else if (tid < nt + ne) {
+            int dd, ss;
+            if (moves_extra(mv, tid - nt, wj, mj, dd, ss)) { d = dd + o; src = ss + o; }
+        }
+        if (d >= 0) val = inv[d];
+        __syncthreads();
+        if (d >= 0) inv[src] = val;
+        __syncthreads();
+    }
+    constexpr int V = kLpermMaxRows / kLpermThreads;
+    for (int c = c0; c < c1; ++c) {
+        T* col = A + r0 + (long long)c * lda;
+        T v[V];
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+            const int i = tid + u * kLpermThreads;
+            if (i < L) v[u] = col[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+            const int i = tid + u * kLpermThreads;
+            if (i < L) col[inv[i]] = v[u];
+        }
+        __syncthreads();
+    }
+}
+
 // Interchange moves of a standalone run of pivots (relative rows).
 // A pivot outside [t, m) is not a legal interchange and is treated as none.
 __global__ __launch_bounds__(kThreads) void moves_kernel(const int* ipiv_rel, int w, int m, int* moves) {
@@ -527,6 +593,27 @@ int launch_lswap(T* A, long long lda, int r0, int w, int m, const int* moves, in
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+template <typename T>
+int launch_lperm(T* A, long long lda, int n, int N, const int* starts_host, const int* starts_dev, const int* moves,
+                 hipStream_t stream) {
+    if (N < 2) return 0;
+    if (n - starts_host[1] > kLpermMaxRows) return -1;
+    int wgs = 0;
+    for (int k = 0; k + 1 < N; ++k) wgs += (starts_host[k + 1] - starts_host[k] + kLpermCols - 1) / kLpermCols;
+    const size_t lds = sizeof(int) * (size_t)(n - starts_host[1]);
+    static bool attr_set = false;           // dynamic LDS beyond the default limit
+    if (!attr_set) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&lperm_kernel<T>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(sizeof(int) * kLpermMaxRows)) != hipSuccess)
+            return -1;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((lperm_kernel<T>), dim3(wgs), dim3(kLpermThreads), lds, stream, A, lda, n, N, starts_dev,
+                       moves);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int launch_moves(const int* ipiv_rel, int w, int m, int* moves, hipStream_t stream) {
     hipLaunchKernelGGL(moves_kernel, dim3(1), dim3(kThreads), 0, stream, ipiv_rel, w, m, moves);
     return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -553,6 +640,8 @@ int launch_l21_half(const float* A, long long lda, int m, int w, H* Lh, long lon
 template int launch_swap_trsm<double, _Float16>(const SwapTrsmArgs<double, _Float16>&, hipStream_t);
 template int launch_swap_trsm<float, _Float16>(const SwapTrsmArgs<float, _Float16>&, hipStream_t);
 template int launch_swap_trsm<float, __bf16>(const SwapTrsmArgs<float, __bf16>&, hipStream_t);
+template int launch_lperm<double>(double*, long long, int, int, const int*, const int*, const int*, hipStream_t);
+template int launch_lperm<float>(float*, long long, int, int, const int*, const int*, const int*, hipStream_t);
 template int launch_lswap<double>(double*, long long, int, int, int, const int*, int, int, hipStream_t, unsigned*,
                                   unsigned*);
 template int launch_lswap<float>(float*, long long, int, int, int, const int*, int, int, hipStream_t, unsigned*,

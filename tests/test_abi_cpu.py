@@ -105,10 +105,12 @@ def _access(t, starts):
     elif t["kind"] == lu.LU_TASK_UPDATE:
         k = t["step"]
         r = set(range(starts[k], starts[k + 1]))
-        ipr = k
+        ipr = {k}
+    elif t["kind"] == lu.LU_TASK_LPERM:
+        ipr = set(range(len(starts) - 1))          # every panel's pivots
     else:
-        ipr = t["step"]
-    return w, r, ipw, ipr
+        ipr = {t["step"]}
+    return w, r, ipw, ipr or set()
 
 
 def _happens_before(tasks):
@@ -125,7 +127,7 @@ def _happens_before(tasks):
     return before
 
 
-def _check_plan(n, starts, depth, tasks):
+def _check_plan(n, starts, depth, tasks, swaps=1):
     N = len(starts) - 1
     # every panel factored once; every (step, column) pair of the trailing
     # matrix updated exactly once; every left swap applied once
@@ -144,7 +146,15 @@ def _check_plan(n, starts, depth, tasks):
             assert cover.get((k, c)) == 1, (k, c)
     assert len(cover) == sum(n - starts[k + 1] for k in range(N))
     lswaps = sorted((t["step"], t["col_begin"], t["col_end"]) for t in tasks if t["kind"] == lu.LU_TASK_LSWAP)
-    assert lswaps == [(k, 0, starts[k]) for k in range(1, N)]
+    lperms = [(t["step"], t["col_begin"], t["col_end"], t["stream"]) for t in tasks if t["kind"] == lu.LU_TASK_LPERM]
+    if swaps == 1:
+        assert lswaps == [(k, 0, starts[k]) for k in range(1, N)] and not lperms
+    else:
+        # one deferred permutation of every finished panel, the last task
+        assert not lswaps
+        assert lperms == ([(N - 1, 0, starts[N - 1], 0)] if N >= 2 else [])
+        if N >= 2:
+            assert tasks[-1]["kind"] == lu.LU_TASK_LPERM
     if depth == 0:
         assert all(t["stream"] == 0 for t in tasks)
     else:
@@ -164,8 +174,8 @@ def _check_plan(n, starts, depth, tasks):
             wi, ri, pwi, pri = acc[i]
             wj, rj, pwj, prj = acc[j]
             assert not (wi & wj) and not (wi & rj) and not (ri & wj), (tasks[j], tasks[i])
-            assert pwi is None or (pwi != prj and pwi != pwj)
-            assert pwj is None or pwj != pri
+            assert pwi is None or (pwi not in prj and pwi != pwj)
+            assert pwj is None or pwj not in pri
 
 
 @pytest.mark.parametrize("n,b,depth", [(10, 4, 0), (10, 4, 1), (13, 4, 2), (64, 16, 1), (70, 16, 2),
@@ -239,6 +249,13 @@ def _run_task(A, ipiv, t, starts, n):
         L11 = np.tril(A[kb:kb + w, kb:kb + w], -1) + np.eye(w)
         A[kb:kb + w, c0:c1] = np.linalg.solve(L11, A[kb:kb + w, c0:c1])
         A[kb + w:, c0:c1] -= A[kb + w:, kb:kb + w] @ A[kb:kb + w, c0:c1]
+    elif t["kind"] == lu.LU_TASK_LPERM:
+        # every panel j >= 1's interchanges on the columns left of it
+        for d in range(starts[1], n):
+            p = ipiv[d]
+            j = max(i for i in range(len(starts) - 1) if starts[i] <= d)
+            if p != d:
+                A[[d, p], 0:starts[j]] = A[[p, d], 0:starts[j]]
     else:
         kb, w = starts[k], starts[k + 1] - starts[k]
         for d in range(kb, kb + w):
@@ -407,3 +424,77 @@ def test_garbage_interchange_lists_stay_in_bounds():
     r = lib.lu_k_moves_check(mv.ctypes.data, w, m, out.ctypes.data)
     assert (r >> 16, r & 0xFFFF) == (2, 2)
     assert out[:8].tolist() == [0, 7, 2, 9, 7, 0, 9, 2]
+
+
+@pytest.mark.parametrize("n,starts,depth", [(24, 4, 1), (30, 8, 2), (37, 8, 0), (37, 8, 2),
+                                            (37, [0, 12, 20, 26, 30, 33, 35, 36, 37], 2),
+                                            (37, [0, 12, 20, 26, 30, 33, 35, 36, 37], 1), (5, [0, 5], 1)])
+def test_deferred_left_interchanges_plan(n, starts, depth):
+    """The plan with the left interchanges deferred to one final LPERM task
+    (what the library runs when a column fits its permutation kernel) is
+    complete and race-free, and executed in random legal orders it gives the
+    oracle's factors and pivots."""
+    import oracle
+    import synth
+    if isinstance(starts, int):
+        starts = _uniform_starts(n, starts)
+    rc, tasks = lu.lu_plan_build_panels_ex(n, starts, depth, 2)
+    assert rc == len(tasks) > 0
+    _check_plan(n, starts, depth, tasks, swaps=2)
+    A0 = np.array(synth.uniform(n, seed=n + 1), order="F")
+    rng = np.random.default_rng(1)
+    results = []
+    for trial in range(3):
+        A = A0.copy()
+        ipiv = np.zeros(n, dtype=np.int64)
+        order = range(len(tasks)) if trial == 0 else _random_legal_order(tasks, rng)
+        for i in order:
+            _run_task(A, ipiv, tasks[i], starts, n)
+        results.append((A, ipiv))
+    for A, ipiv in results[1:]:
+        assert np.array_equal(A, results[0][0]) and np.array_equal(ipiv, results[0][1])
+    LU, ip, info = oracle.getrf(A0)
+    assert np.array_equal(results[0][1], ip)
+    assert np.abs(results[0][0] - LU).max() <= 1e-10 * max(1.0, np.abs(LU).max())
+
+
+def test_deferred_permutation_composition_matches_sequential_swaps():
+    """The composition the permutation kernel computes, modelled in numpy from
+    its description: for panel k, inv starts as the identity on rows >= r0 =
+    s_k+1; the panels j = N-1 down to k+1 each set inv[src] = inv[dst] for
+    their composed moves (new[dst] = old[src], here built from ipiv by
+    simulating the panel's interchanges); the column is written new[inv[i]] =
+    old[i].  It must equal applying ipiv[r0:] row swaps one by one."""
+    rng = np.random.default_rng(5)
+    for trial in range(30):
+        n = int(rng.integers(8, 60))
+        cuts = sorted(set(int(x) for x in rng.integers(1, n, int(rng.integers(1, 6)))))
+        starts = [0] + cuts + [n]
+        ipiv = np.array([int(rng.integers(d, n)) for d in range(n)])
+        N = len(starts) - 1
+
+        def moves_of(j):
+            # new[dst] = old[src] for the rows the panel's interchanges move
+            idx = np.arange(n)
+            for d in range(starts[j], starts[j + 1]):
+                p = ipiv[d]
+                idx[[d, p]] = idx[[p, d]]
+            return [(r, idx[r]) for r in range(n) if idx[r] != r]
+
+        for k in range(N - 1):
+            r0 = starts[k + 1]
+            col = rng.standard_normal(n)
+            want = col.copy()
+            for d in range(r0, n):
+                p = ipiv[d]
+                want[[d, p]] = want[[p, d]]
+            inv = np.arange(n - r0)
+            for j in range(N - 1, k, -1):
+                mv = moves_of(j)
+                old = inv.copy()
+                for dst, src in mv:
+                    inv[src - r0] = old[dst - r0]
+            got = col.copy()
+            seg = col[r0:].copy()
+            got[r0 + inv] = seg
+            assert np.array_equal(got, want), (trial, k)
