@@ -8,9 +8,15 @@ One step = the whole hot path on one batch of synthetic input resident in HBM:
   3. lu_solve_ir in mixed precision (FP16 trailing GEMM, FP32 panel/TRSM, FP64
      refinement) on the row-dominant matrix of the same size.
 `value` is the FP64 factorization rate 2/3 n^3 / t_factor (median over the
-timed steps, HIP events on the stream the factorization runs on).  After the
-timed steps: the Cholesky, QR and band-reduction legs (each timed the same
-way), then the CPU oracles on bounded samples.
+timed steps, HIP events on the stream the factorization runs on).  The
+row-dominant matrix and its right-hand side come from the seeded host
+generators (synth), so that the refined solution can be compared with the
+oracle's FP64 solution stored in tests/golden (when one exists for n).
+After the timed steps, untimed for the headline: one FP64 and one mixed
+factorization with the library's per-launch GEMM timing hook (the rooflines),
+optionally the standalone GEMM ceiling (--gemm-ceiling), the Cholesky, QR and
+band-reduction legs (each timed like the LU), then the CPU oracles on bounded
+samples.
 
 Prints one JSON line.  --gpus N with N > 1 exits: the path runs on one GPU.
 """
@@ -26,14 +32,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "LU GFLOPS (2/3·n³/t) at n=32768, FP64 vs mixed+IR; % MFMA peak; IR time-to-solve"
 FP64_PEAK_TFLOPS = 78.6
+FP16_PEAK_TFLOPS = 2516.6     # dense FP16/BF16 matrix peak
+HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch of the FP64 trailing GEMM, from two rocprofv3 --pmc passes
 # (FETCH_SIZE, then WRITE_SIZE) over one bench step, each scaled by what the same
 # counter reads for the bench's own n*n*8-byte device copy (see
 # profiles/gemm_f64_n32768_hbm_traffic.md).  Valid only for the schedule and the
 # GEMM source it was measured with; otherwise the bench reports null.
-GEMM_TRAFFIC = {"n": 32768, "b": 256, "depth": 2, "taper": 1, "gemm_source_sha256_16": "d36504d1a6bc4cb6",
-                "bytes_per_launch": 2022112872}
+GEMM_TRAFFIC = {"n": 32768, "b": 256, "depth": 2, "taper": 1, "gemm_source_sha256_16": "43f530c178969ad6",
+                "bytes_per_launch": 2098771685}
 
 
 def gemm_source_hash():
@@ -59,6 +67,45 @@ def gemm_algorithmic_bytes(lu, n, b, depth, taper):
             tot += 16.0 * m * w + 8.0 * m * wk + 8.0 * wk * w
             cnt += 1
     return tot / max(cnt, 1)
+
+
+def oracle_solution(n, seed=1):
+    """The oracle's FP64 solution of the seeded row-dominant system of size n,
+    as written by tests/golden/make_xo.py (float64[n]), with its metadata, or
+    (None, None) when none is stored for n."""
+    import numpy as np
+    stem = os.path.join(ROOT, "tests", "golden", "xo_dominant_n%d_s%d" % (n, seed))
+    if not (os.path.exists(stem + ".npy") and os.path.exists(stem + ".json")):
+        return None, None
+    with open(stem + ".json") as f:
+        meta = json.load(f)
+    return np.load(stem + ".npy"), meta
+
+
+def same_matrix(A, fp):
+    """Does the host matrix A carry the fingerprint (trace and a hash of
+    sampled entries) recorded with the oracle's solution?"""
+    import hashlib
+    import numpy as np
+    i = np.asarray(fp["rows"])
+    j = np.asarray(fp["cols"])
+    vals = np.ascontiguousarray(A[i, j])
+    return hashlib.sha256(vals.tobytes()).hexdigest() == fp["sha256_samples"] and float(np.trace(A)) == fp["trace"]
+
+
+def cpu_info():
+    """Host CPU facts for the baseline: online CPUs, the process's affinity
+    mask size and the CPU model."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "cpu_model": model}
 
 
 def device_spd(lu, n, seed, A):
@@ -216,7 +263,7 @@ def cpu_baseline(budget_s=20.0):
     extrapolation from shorter runs to take about budget_s."""
     import oracle
     import synth
-    cores = min(16, len(os.sched_getaffinity(0)))
+    cores = len(os.sched_getaffinity(0))
     n, t = 1024, 0.0
     for _ in range(4):
         A = synth.uniform(n, seed=1)
@@ -226,9 +273,11 @@ def cpu_baseline(budget_s=20.0):
         if t >= 0.4 * budget_s or n >= 16384:
             break
         n = min(16384, max(n + 256, int(n * (budget_s / max(t, 1e-3)) ** (1 / 3)))) // 256 * 256
-    return {"value": round((2.0 / 3.0) * n ** 3 / t / 1e9, 3), "unit": "GFLOP/s", "cores": cores,
-            "kind": "oracle",
-            "sample": "one FP64 partial-pivoting LU of a uniform[-1,1) %dx%d matrix (%.1f s)" % (n, n, t)}
+    out = {"value": round((2.0 / 3.0) * n ** 3 / t / 1e9, 3), "unit": "GFLOP/s", "cores": cores,
+           "kind": "oracle",
+           "sample": "one FP64 partial-pivoting LU of a uniform[-1,1) %dx%d matrix (%.1f s)" % (n, n, t)}
+    out.update(cpu_info())
+    return out
 
 
 def oracle_rate(kind, budget_s=8.0):
@@ -238,7 +287,7 @@ def oracle_rate(kind, budget_s=8.0):
     (4n^3/3), 'band' the band reduction (8n^3/3, w = 384; single-threaded)."""
     import oracle
     import synth
-    cores = min(16, len(os.sched_getaffinity(0)))
+    cores = len(os.sched_getaffinity(0))
     flops = {"chol": 1.0 / 3.0, "qr": 4.0 / 3.0, "band": 8.0 / 3.0}[kind]
     n, t = 512, 0.0
     for _ in range(5):
@@ -281,14 +330,18 @@ def main():
     ap.add_argument("--no-qr", action="store_true", help="skip the QR measurement")
     ap.add_argument("--no-band", action="store_true", help="skip the band-reduction measurement")
     ap.add_argument("--band-w", type=int, default=384, help="bandwidth of the band-reduction leg")
+    ap.add_argument("--gemm-ceiling", action="store_true",
+                    help="also time the library's FP64 trailing GEMM alone on the first update's shape")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the hot path is built and measured on a single MI355X); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
     import paper_1804_07017_amd as lu
+    import synth
     lu.load()
     torch.cuda.set_device(0)
     n = args.n
@@ -303,12 +356,17 @@ def main():
     x = torch.empty(n, dtype=torch.float64, device=dev)
     ipiv = torch.zeros(n, dtype=torch.int32, device=dev)
     D = None
+    xo = None
     if not args.no_ir:
-        D = lu.colmajor(n)
-        D.uniform_(-1.0, 1.0, generator=g)
-        rowsum = D.abs().sum(dim=1)
-        D.diagonal().copy_(rowsum)
-        del rowsum
+        # the row-dominant system from the host generators (seed 1): the one
+        # the oracle's stored solution belongs to
+        xo, meta = oracle_solution(n)
+        Dh = synth.dominant(n, seed=1)
+        if xo is not None and not same_matrix(Dh, meta["fingerprint"]):
+            raise RuntimeError("the regenerated row-dominant matrix differs from the oracle's")
+        D = lu.to_device(Dh)
+        del Dh
+        bd = torch.from_numpy(synth.rhs(n, seed=1)[:, 0].copy()).to(dev)
         X = torch.empty(n, dtype=torch.float64, device=dev)
     stream = torch.cuda.Stream()
     sched = None
@@ -320,6 +378,19 @@ def main():
         used = (sched[0] or used[0], sched[1], sched[2] or used[2], sched[3] or used[3])
     taper_on = 1 if used[3] > 0 else 0
     torch.cuda.synchronize()
+
+    def factor_once():
+        """FP64 factorization of the pristine matrix; returns its event time (ms)."""
+        with torch.cuda.stream(stream):
+            A.copy_(A0)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            r = lu.lu_factor_ex(A, ipiv, prec=lu.LU_FP64, sched=sched, stream=stream)
+            assert r == 0, r
+            e1.record(stream)
+        stream.synchronize()
+        return e0.elapsed_time(e1)
 
     def step(rec):
         with torch.cuda.stream(stream):
@@ -339,7 +410,7 @@ def main():
             if D is not None:
                 stream.synchronize()
                 t0 = time.perf_counter()
-                st, it, res = lu.lu_solve_ir(D, bvec, X, prec=lu.LU_MIXED_FP16, max_iter=10, stream=stream)
+                st, it, res = lu.lu_solve_ir(D, bd, X, prec=lu.LU_MIXED_FP16, max_iter=10, stream=stream)
                 stream.synchronize()
                 ir = (st, it, res, (time.perf_counter() - t0) * 1e3)
         stream.synchronize()
@@ -354,7 +425,6 @@ def main():
         print("bench: factorization error %d" % rc, file=sys.stderr)
         sys.exit(1)
 
-    lu.lu_k_timing(1)
     recs = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -364,14 +434,49 @@ def main():
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    lu.lu_k_timing(0)
-    rc_t, gemm_ms, gemm_flops, gemm_launches = lu.lu_k_timing_read()
 
     # correctness of the last step: HPL residual of the FP64 solve (device GEMV in FP64)
     with torch.no_grad():
         A0r = A0.abs().sum(dim=1).max().item()
         r = (A0 @ x - bvec).abs().max().item()
         hpl = r / (2.0 ** -53 * (A0r * x.abs().max().item() + bvec.abs().max().item()) * n)
+    err_vs_oracle = None
+    if xo is not None:
+        xs = X.cpu().numpy()
+        err_vs_oracle = float(np.abs(xs - xo).max() / np.abs(xo).max())
+
+    # untimed passes for the rooflines: the per-launch GEMM timing hook records
+    # events around every trailing-GEMM launch of one FP64 factorization and of
+    # one mixed-precision factorization (FP32 working copy of the dominant matrix)
+    print("bench: roofline passes", file=sys.stderr, flush=True)
+    t_mixed = None
+    D32 = ip32 = None
+
+    def mixed_factor_once():
+        W = D32.clone()
+        with torch.cuda.stream(stream):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            r = lu.lu_factor_ex(W, ip32, prec=lu.LU_MIXED_FP16, stream=stream)
+            assert r == 0, r
+            e1.record(stream)
+        stream.synchronize()
+        del W
+        return e0.elapsed_time(e1)
+
+    if D is not None:
+        D32 = D.to(torch.float32)
+        ip32 = torch.zeros(n, dtype=torch.int32, device=dev)
+        mixed_factor_once()                       # warm-up, not recorded
+    lu.lu_k_timing(1)
+    t_hooked = factor_once()
+    if D is not None:
+        t_mixed = mixed_factor_once()
+        del D32, ip32
+    lu.lu_k_timing(0)
+    rc_t, gemm_ms, gemm_flops, gemm_launches = lu.lu_k_timing_read()
+    rc_h, half_ms, half_flops, half_bytes, half_launches = lu.lu_k_timing_read_ex(1)
 
     t_fact = statistics.median(r[0] for r in recs)
     t_solve = statistics.median(r[1] for r in recs)
@@ -400,10 +505,24 @@ def main():
     if D is not None:
         irs = [r[2] for r in recs]
         t_ir = statistics.median(i[3] for i in irs)
+        mgf = flops / (t_mixed * 1e-3) / 1e9
         out["mixed_ir"] = {"status": irs[-1][0], "iters": irs[-1][1], "hpl_resid": irs[-1][2],
                            "tts_ms": round(t_ir, 3),
                            "speedup_vs_fp64_tts": round((t_fact + t_solve) / t_ir, 3),
-                           "effective_gflops": round(flops / (t_ir * 1e-3) / 1e9, 1)}
+                           "effective_gflops": round(flops / (t_ir * 1e-3) / 1e9, 1),
+                           "err_vs_oracle": err_vs_oracle,
+                           "t_factor_mixed_ms": round(t_mixed, 3),
+                           "factor_gflops": round(mgf, 1),
+                           "pct_fp16_peak": round(100 * mgf / 1e3 / FP16_PEAK_TFLOPS, 3)}
+        if rc_h == 0 and half_launches > 0:
+            gbs = half_bytes / (half_ms * 1e-3) / 1e9
+            out["mixed_ir"]["roofline"] = {
+                "bound": "hbm", "kernel": "gemm_half_sub<_Float16> (mixed trailing update)",
+                "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                "launches": half_launches, "avg_launch_us": round(half_ms * 1e3 / half_launches, 2),
+                "avg_launch_bytes": round(half_bytes / half_launches),
+                "mfma_tflops": round(half_flops / (half_ms * 1e-3) / 1e12, 1)}
     if rc_t == 0 and gemm_launches > 0:
         ach = gemm_flops / (gemm_ms * 1e-3) / 1e12
         traffic = None
@@ -419,7 +538,35 @@ def main():
                                                                                         taper_on)),
                            "launches": gemm_launches,
                            "avg_launch_us": round(gemm_ms * 1e3 / gemm_launches, 2),
-                           "avg_launch_gflop": round(gemm_flops / gemm_launches / 1e9, 3)}
+                           "avg_launch_gflop": round(gemm_flops / gemm_launches / 1e9, 3),
+                           "hooked_factor_ms": round(t_hooked, 3)}
+    if args.gemm_ceiling:
+        # the library's trailing GEMM alone on the first update's shape
+        bb = used[0]
+        M = N = n - bb
+        Am = lu.colmajor(M, bb)
+        Am.uniform_(-1.0, 1.0, generator=g)
+        Bm = lu.colmajor(bb, N)
+        Bm.uniform_(-1.0, 1.0, generator=g)
+        ts = []
+        for rep in range(6):
+            with torch.cuda.stream(stream):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                r = lu.lu_k_gemm(Am, Bm, A[:M, :N], prec=lu.LU_FP64, stream=stream)
+                assert r == 0, r
+                e1.record(stream)
+            stream.synchronize()
+            if rep:
+                ts.append(e0.elapsed_time(e1))
+        tc = statistics.median(ts)
+        tf = 2.0 * M * N * bb / (tc * 1e-3) / 1e12
+        out["gemm_ceiling"] = {"kernel": "gemm_nn_sub<double,16> alone", "m": M, "n": N, "k": bb,
+                               "ms": round(tc, 3), "tflops": round(tf, 2),
+                               "frac_of_peak": round(tf / FP64_PEAK_TFLOPS, 4),
+                               "lu_pct_of_ceiling": round(100 * gflops / 1e3 / tf, 2)}
+        del Am, Bm
     if not args.no_chol:
         out["cholesky"] = cholesky_leg(lu, n, args.steps, A0, A)
     if not args.no_qr:

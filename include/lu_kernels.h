@@ -55,6 +55,13 @@ int lu_k_laswp(lu_precision_t prec, int m, int w, int ncols, const int* ipiv_rel
 int lu_k_timing(int enable);
 int lu_k_timing_read(double* ms, double* flops, int* launches);
 
+/* As lu_k_timing_read for one kind of launch: kind 0 the FP64/FP32 trailing
+ * GEMM, kind 1 the FP16/BF16 trailing GEMM of the mixed precisions; bytes
+ * (host) receives the summed algorithmic HBM bytes of those launches (kind 1:
+ * the FP32 C block read and written, the half operands and scales read once;
+ * kind 0: 0).  Errors: -1 kind, -2 ms, -3 flops, -4 bytes, -5 launches. */
+int lu_k_timing_read_ex(int kind, double* ms, double* flops, double* bytes, int* launches);
+
 /* Host only (no device call): the moves a trailing kernel takes from a
  * composed interchange list (host int[2 + 4*512]: [0] top count, [1] extra
  * count, top (dst, src) pairs from [2], extra pairs from [2 + 2*512]; rows

@@ -79,6 +79,8 @@ _SIGS = {
     "lu_k_timing": (_I, [_I]),
     "lu_k_timing_read": (_I, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(_I)]),
+    "lu_k_timing_read_ex": (_I, [_I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I)]),
 }
 
 
@@ -402,3 +404,14 @@ def lu_k_timing_read():
     n = ctypes.c_int(0)
     rc = load().lu_k_timing_read(ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(n))
     return rc, ms.value, fl.value, n.value
+
+
+def lu_k_timing_read_ex(kind):
+    """(rc, summed ms, summed flops, summed algorithmic bytes, launches) of the
+    recorded trailing-GEMM launches of one kind (0 FP64/FP32, 1 FP16/BF16)."""
+    ms = ctypes.c_double(0)
+    fl = ctypes.c_double(0)
+    by = ctypes.c_double(0)
+    n = ctypes.c_int(0)
+    rc = load().lu_k_timing_read_ex(int(kind), ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(by), ctypes.byref(n))
+    return rc, ms.value, fl.value, by.value, n.value

@@ -29,15 +29,17 @@ namespace lu {
 namespace {
 std::map<int, DeviceState*> g_states;
 
-// optional per-launch timing of the trailing GEMM
+// optional per-launch timing of the trailing GEMMs: kind 0 = the FP64/FP32
+// trailing GEMM, kind 1 = the FP16/BF16 one of the mixed precisions
 struct GemmTiming {
     bool on = false;
     std::vector<hipEvent_t> ev;     // start/stop pairs
-    std::vector<double> flops;
+    std::vector<double> flops, bytes;
+    std::vector<int> kind;
     size_t used = 0;                // pairs in use
 } g_timing;
 
-int timed_begin(hipStream_t st, int M, int N, int K, hipEvent_t* stop) {
+int timed_begin(hipStream_t st, int M, int N, int K, hipEvent_t* stop, int kind = 0, double bytes = 0.0) {
     *stop = nullptr;
     if (!g_timing.on) return 0;
     if (g_timing.used * 2 + 2 > g_timing.ev.size()) {
@@ -50,7 +52,11 @@ int timed_begin(hipStream_t st, int M, int N, int K, hipEvent_t* stop) {
     hipEvent_t start = g_timing.ev[2 * g_timing.used];
     *stop = g_timing.ev[2 * g_timing.used + 1];
     g_timing.flops.resize(g_timing.used + 1);
+    g_timing.bytes.resize(g_timing.used + 1);
+    g_timing.kind.resize(g_timing.used + 1);
     g_timing.flops[g_timing.used] = 2.0 * M * (double)N * K;
+    g_timing.bytes[g_timing.used] = bytes;
+    g_timing.kind[g_timing.used] = kind;
     g_timing.used++;
     return hipEventRecord(start, st) == hipSuccess ? 0 : LU_ERR_HIP;
 }
@@ -431,12 +437,17 @@ int execute(DeviceState* s, int n, T* A, long long lda, int* ipiv, int* info, co
             const int M = n - kb - wk, Nc = t.col_end - t.col_begin;
             if (M > 0) {
                 if (mixed) {
+                    // algorithmic bytes: FP32 C read and written, the half operands and the scales read once
+                    hipEvent_t stop;
+                    const double hb = 8.0 * M * (double)Nc + 2.0 * wk * ((double)M + Nc) + 4.0 * ((double)M + Nc);
+                    if ((rc = timed_begin(st, M, Nc, wk, &stop, 1, hb))) return rc;
                     if (launch_gemm_half<H>(M, Nc, wk, Lh + (long long)(kb + wk) * ldh + kb, (int)ldh,
                                             Uh + (long long)t.col_begin * lduh + kb, (int)lduh,
                                             rs + (size_t)k * n + (kb + wk), cs + (size_t)k * n + t.col_begin,
                                             reinterpret_cast<float*>(A) + (kb + wk) + (long long)t.col_begin * lda,
                                             (int)lda, st, skip_t ? gemm_claim() : XcdClaim()))
                         return LU_ERR_HIP;
+                    if (stop) LU_HIP(hipEventRecord(stop, st));
                 } else {
                     hipEvent_t stop;
                     if ((rc = timed_begin(st, M, Nc, wk, &stop))) return rc;
@@ -716,22 +727,37 @@ int lu_k_timing(int enable) {
     return 0;
 }
 
-int lu_k_timing_read(double* ms, double* flops, int* launches) {
-    if (!ms) return -1;
-    if (!flops) return -2;
-    if (!launches) return -3;
-    double t = 0, f = 0;
+int lu_k_timing_read_ex(int kind, double* ms, double* flops, double* bytes, int* launches) {
+    if (kind != 0 && kind != 1) return -1;
+    if (!ms) return -2;
+    if (!flops) return -3;
+    if (!bytes) return -4;
+    if (!launches) return -5;
+    double t = 0, f = 0, b = 0;
+    int cnt = 0;
     for (size_t i = 0; i < lu::g_timing.used; ++i) {
+        if (lu::g_timing.kind[i] != kind) continue;
         float e = 0.f;
         LU_HIP(hipEventSynchronize(lu::g_timing.ev[2 * i + 1]));
         LU_HIP(hipEventElapsedTime(&e, lu::g_timing.ev[2 * i], lu::g_timing.ev[2 * i + 1]));
         t += e;
         f += lu::g_timing.flops[i];
+        b += lu::g_timing.bytes[i];
+        ++cnt;
     }
     *ms = t;
     *flops = f;
-    *launches = (int)lu::g_timing.used;
+    *bytes = b;
+    *launches = cnt;
     return 0;
+}
+
+int lu_k_timing_read(double* ms, double* flops, int* launches) {
+    if (!ms) return -1;
+    if (!flops) return -2;
+    if (!launches) return -3;
+    double b;
+    return lu_k_timing_read_ex(0, ms, flops, &b, launches);
 }
 
 int lu_k_moves_check(const int* moves, int w, int m, int* out) {

@@ -64,21 +64,22 @@ __device__ __forceinline__ int tile_of_block(int nt, bool xcd_chunks) {
 // same column block.  LOW: only C's lower triangle is updated -- element
 // (i, j) of C when i + diag >= j -- tiles wholly above it are skipped and
 // tiles across it store only their lower part.
-template <typename T, int BK, bool TB, bool LOW, bool ZERO = false>
+template <typename T, int BK, bool TB, bool LOW, bool ZERO = false, int BM = kBM>
 __device__ __forceinline__ void gemm_tile(int L, int M, int N, int K, const T* __restrict__ A, int lda,
                                           const T* __restrict__ B, int ldb, T* __restrict__ C, int ldc,
                                           int diag) {
     typedef typename Acc<T>::type V4;
     constexpr int PA = 2, PB = 1;
-    __shared__ T As[2][BK][kBM + PA];
+    constexpr int WTM = BM / 2, RB = WTM / 16;      // rows per wave and 16-row blocks per wave
+    __shared__ T As[2][BK][BM + PA];
     __shared__ T Bs[2][kBN][BK + PB];
 
-    const int tiles_m = (M + kBM - 1) / kBM, tiles_n = (N + kBN - 1) / kBN;
+    const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + kBN - 1) / kBN;
     int tm, tn;
     tile_coords(L, tiles_m, tiles_n, tm, tn);
-    const int m0 = tm * kBM, n0 = tn * kBN;
+    const int m0 = tm * BM, n0 = tn * kBN;
     if constexpr (LOW) {
-        if (m0 + kBM - 1 + diag < n0) return;          // the whole tile lies above the diagonal
+        if (m0 + BM - 1 + diag < n0) return;          // the whole tile lies above the diagonal
     }
     const int tid = threadIdx.x;
     const int wave = tid / 64, lane = tid % 64;
@@ -87,16 +88,16 @@ __device__ __forceinline__ void gemm_tile(int L, int M, int N, int K, const T* _
 
     // Tiles inside the matrix (all but the last tile row and column) take a
     // branch-free path: no per-element bounds checks, B read two k at a time.
-    const bool interior = m0 + kBM <= M && n0 + kBN <= N;
+    const bool interior = m0 + BM <= M && n0 + kBN <= N;
     const bool vecb = !TB && interior && (reinterpret_cast<unsigned long long>(B) % (2 * sizeof(T))) == 0 &&
                       (ldb % 2) == 0;
     // LOW: tiles wholly below the diagonal store everything
     const bool full = !LOW || m0 + diag >= n0 + kBN - 1;
 
     // accumulators start from C (ZERO: from 0, C is only written)
-    V4 acc[4][4];
+    V4 acc[RB][4];
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
+    for (int rb = 0; rb < RB; ++rb) {
         if constexpr (ZERO) {
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb)
@@ -104,7 +105,7 @@ __device__ __forceinline__ void gemm_tile(int L, int M, int N, int K, const T* _
                 for (int r = 0; r < 4; ++r) acc[rb][cb][r] = T(0);
             continue;
         }
-        const int row = m0 + wm * 64 + rb * 16 + l16;
+        const int row = m0 + wm * WTM + rb * 16 + l16;
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
 #pragma unroll
@@ -117,11 +118,11 @@ __device__ __forceinline__ void gemm_tile(int L, int M, int N, int K, const T* _
     }
 
     // global -> register staging
-    constexpr int AL = BK * kBM / kThreads;   // A elements per thread
+    constexpr int AL = BK * BM / kThreads;    // A elements per thread
     constexpr int BL = BK * kBN / kThreads;   // B elements per thread
     T ra[AL], rbv[BL];
-    const int a_row = tid % kBM, a_k0 = tid / kBM;              // A: rows contiguous
-    constexpr int AKS = kThreads / kBM;
+    const int a_row = tid % BM, a_k0 = tid / BM;                // A: rows contiguous
+    constexpr int AKS = kThreads / BM;
     const int b_col = tid / (kThreads / kBN), b_kh = tid % (kThreads / kBN);   // B: k contiguous
     constexpr int BKS = BK / (kThreads / kBN);
     const int t_col = tid % kBN, t_k0 = tid / kBN;                               // B^T: j contiguous
@@ -189,13 +190,13 @@ __device__ __forceinline__ void gemm_tile(int L, int M, int N, int K, const T* _
         if (kt + 1 < nk) load((kt + 1) * BK);
 #pragma unroll
         for (int ks = 0; ks < BK / 4; ++ks) {
-            T af[4], bf[4];
+            T af[RB], bf[4];
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb) af[rb] = As[cur][ks * 4 + lg][wm * 64 + rb * 16 + l16];
+            for (int rb = 0; rb < RB; ++rb) af[rb] = As[cur][ks * 4 + lg][wm * WTM + rb * 16 + l16];
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) bf[cb] = Bs[cur][wn * 64 + cb * 16 + l16][ks * 4 + lg];
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb)
+            for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = mfma(bf[cb], af[rb], acc[rb][cb]);
         }
@@ -204,8 +205,8 @@ __device__ __forceinline__ void gemm_tile(int L, int M, int N, int K, const T* _
     }
 
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
-        const int row = m0 + wm * 64 + rb * 16 + l16;
+    for (int rb = 0; rb < RB; ++rb) {
+        const int row = m0 + wm * WTM + rb * 16 + l16;
         if (interior || row < M) {
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) {
@@ -220,12 +221,17 @@ __device__ __forceinline__ void gemm_tile(int L, int M, int N, int K, const T* _
     }
 }
 
+// The LU's trailing update runs 64 x 128 tiles (each wave 32 x 64), three
+// work-groups per CU: measured faster than 128 x 128 at two per CU for the
+// short k of a panel (FP64, 32768^2 x 256: 9.6 against 10.3 ms).  Element
+// (i, j) sees the same MFMA sequence in either tile shape.
+constexpr int kLuBM = 64;
 template <typename T, int BK>
-__global__ __launch_bounds__(kThreads, 2) void gemm_nn_sub(int M, int N, int K, const T* __restrict__ A,
+__global__ __launch_bounds__(kThreads, 3) void gemm_nn_sub(int M, int N, int K, const T* __restrict__ A,
                                                             int lda, const T* __restrict__ B, int ldb,
                                                             T* __restrict__ C, int ldc) {
-    const int nt = ((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
-    gemm_tile<T, BK, false, false>(tile_of_block(nt, true), M, N, K, A, lda, B, ldb, C, ldc, 0);
+    const int nt = ((M + kLuBM - 1) / kLuBM) * ((N + kBN - 1) / kBN);
+    gemm_tile<T, BK, false, false, false, kLuBM>(tile_of_block(nt, true), M, N, K, A, lda, B, ldb, C, ldc, 0);
 }
 
 // Tile claiming for a launch beside a panel that holds XCD 0 (the trailing
@@ -274,12 +280,14 @@ __device__ __forceinline__ void claimed_tiles(unsigned* ctr, unsigned* next, int
 }
 
 template <typename T, int BK>
-__global__ __launch_bounds__(kThreads, 2) void gemm_nn_sub_x7(int M, int N, int K, const T* __restrict__ A,
+__global__ __launch_bounds__(kThreads, 3) void gemm_nn_sub_x7(int M, int N, int K, const T* __restrict__ A,
                                                                int lda, const T* __restrict__ B, int ldb,
                                                                T* __restrict__ C, int ldc, unsigned* ctr,
                                                                unsigned* next) {
-    const int nt = ((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
-    claimed_tiles(ctr, next, nt, [&](int L) { gemm_tile<T, BK, false, false>(L, M, N, K, A, lda, B, ldb, C, ldc, 0); });
+    const int nt = ((M + kLuBM - 1) / kLuBM) * ((N + kBN - 1) / kBN);
+    claimed_tiles(ctr, next, nt, [&](int L) {
+        gemm_tile<T, BK, false, false, false, kLuBM>(L, M, N, K, A, lda, B, ldb, C, ldc, 0);
+    });
 }
 
 // The same product for the Householder block updates (QR, band reduction):
@@ -507,10 +515,10 @@ template <typename T>
 int launch_gemm(int M, int N, int K, const T* A, int lda, const T* B, int ldb, T* C, int ldc,
                 hipStream_t stream, XcdClaim claim) {
     if (M <= 0 || N <= 0 || K <= 0) return 0;
-    const int tiles = ((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
+    const int tiles = ((M + kLuBM - 1) / kLuBM) * ((N + kBN - 1) / kBN);
     if (claim.ctr)
-        hipLaunchKernelGGL((gemm_nn_sub_x7<T, 16>), dim3(x7_grid(claim.cus, tiles)), dim3(kThreads), 0, stream, M, N,
-                           K, A, lda, B, ldb, C, ldc, claim.ctr, claim.next);
+        hipLaunchKernelGGL((gemm_nn_sub_x7<T, 16>), dim3(std::min(3 * claim.cus, tiles + tiles / 7 + 8)),
+                           dim3(kThreads), 0, stream, M, N, K, A, lda, B, ldb, C, ldc, claim.ctr, claim.next);
     else
         hipLaunchKernelGGL((gemm_nn_sub<T, 16>), dim3(tiles), dim3(kThreads), 0, stream, M, N, K, A, lda, B,
                            ldb, C, ldc);

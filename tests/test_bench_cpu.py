@@ -24,7 +24,27 @@ def test_oracle_rate_fields(kind):
 def test_cpu_baseline_fields():
     r = bench.cpu_baseline(budget_s=0.05)
     assert r["kind"] == "oracle" and r["value"] > 0 and r["cores"] >= 1
+    # every core of the affinity mask, and the host described
+    assert r["cores"] == len(os.sched_getaffinity(0)) == r["affinity"]
+    assert r["nproc"] >= r["affinity"] and r["cpu_model"]
     json.dumps(r)
+
+
+def test_oracle_solution_fingerprint():
+    """The bench compares the refined n = 32768 solution with the oracle's
+    stored one only after checking that the regenerated row-dominant matrix
+    is the one the oracle solved (here at a small size: the fingerprint of a
+    matrix matches itself and not a perturbed copy)."""
+    import synth
+    from tests.golden import make_xo
+    A = synth.dominant(300, seed=1)
+    fp = make_xo.fingerprint(A)
+    assert bench.same_matrix(A, fp)
+    B = A.copy()
+    i, j = fp["rows"][7], fp["cols"][7]
+    B[i, j] += 1e-13
+    assert not bench.same_matrix(B, fp)
+    assert bench.oracle_solution(300) == (None, None)
 
 
 def test_several_gpus_exit_with_message():
