@@ -58,6 +58,14 @@ template <int S>
 __device__ __forceinline__ void put_value(unsigned long long* dst, float v, unsigned tag) {
     xstore_s<S>(&dst[0], tagged(tag, __float_as_uint(v)));
 }
+// The same payload words written straight to the work-group's LDS copy
+// (xbuf), for a launch of one work-group, which exchanges nothing.
+__device__ __forceinline__ void put_lds(unsigned* w, double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    w[0] = (unsigned)(b >> 32);
+    w[1] = (unsigned)b;
+}
+__device__ __forceinline__ void put_lds(unsigned* w, float v) { w[0] = __float_as_uint(v); }
 __device__ __forceinline__ double get_value(const unsigned* w, double*) {
     return __longlong_as_double((long long)(((unsigned long long)w[0] << 32) | w[1]));
 }
@@ -384,14 +392,25 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
             //    then the candidate's block row and row d, each by the wave that
             //    owns the row: lane t supplies block column t (finished columns
             //    from the LDS copy, the rest read from the owner's registers)
+            // A launch of one work-group has no one to exchange with: the same
+            // words go straight to its LDS copy (xbuf: the slot's SR words,
+            // then row d), and the polling below is skipped.
+            const bool solo = P == 1;
             {
                 unsigned long long* slot = xa + (size_t)g * X::SW;
                 if (tid == 0) {
-                    xstore_s<S>(&slot[0], tagged(tag, (unsigned)bi));
-                    put_value<S>(&slot[1], bv, tag);
+                    if (solo) {
+                        sh.xbuf[0] = (unsigned)bi;
+                        put_lds(&sh.xbuf[1], bv);
+                    } else {
+                        xstore_s<S>(&slot[0], tagged(tag, (unsigned)bi));
+                        put_value<S>(&slot[1], bv, tag);
+                    }
                 }
-                if (bi == 0x7fffffff && tid < NB)      // no candidate here: a zero row completes the slot
-                    put_value<S>(&slot[1 + X::WPV + tid * X::WPV], T(0), tag);
+                if (bi == 0x7fffffff && tid < NB) {    // no candidate here: a zero row completes the slot
+                    if (solo) put_lds(&sh.xbuf[1 + X::WPV + tid * X::WPV], T(0));
+                    else put_value<S>(&slot[1 + X::WPV + tid * X::WPV], T(0), tag);
+                }
 #pragma unroll
                 for (int q = 0; q < RPT; ++q) {
                     const int i = row_of(q);
@@ -407,9 +426,13 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
                                 const T r = lane_t(reg[q][s], ol);
                                 if (lane == j + s) v = r;
                             }
-                            unsigned long long* dst = which == 0 ? slot + 1 + X::WPV
-                                                                 : xa + (size_t)kMaxPanelWgs * X::SW;
-                            if (lane < NB) put_value<S>(&dst[lane * X::WPV], v, tag);
+                            if (solo) {
+                                if (lane < NB) put_lds(&sh.xbuf[(which == 0 ? 1 + X::WPV : X::SR) + lane * X::WPV], v);
+                            } else {
+                                unsigned long long* dst = which == 0 ? slot + 1 + X::WPV
+                                                                     : xa + (size_t)kMaxPanelWgs * X::SW;
+                                if (lane < NB) put_value<S>(&dst[lane * X::WPV], v, tag);
+                            }
                         }
                     }
                 }
@@ -417,9 +440,10 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
             // 3. phase A: every work-group's header and row d, polled until all
             //    words carry this step's tag (bounded wait); one word per thread
             const long long t0 = wall_clock64();
-            int poll = 0;
             bool failed = false;
-            {
+            if (solo) {
+                lds_barrier();
+            } else {
                 // every work-group's slot (header and candidate row) and row d:
                 // thread t polls words t, t + threads, ... until all carry this
                 // step's tag (bounded wait; thread 0 also watches the error
@@ -452,8 +476,7 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs<T> a) {
                     }
                     if (pending && (errw != 0u || wall_clock64() - t0 > a.spin_limit)) { st = 3; break; }
                 }
-                st = wg_or(st, sh.orslot, poll & 1, kPanelThreads / kWave);
-                ++poll;
+                st = wg_or(st, sh.orslot, 0, kPanelThreads / kWave);
                 failed = (st & 2) != 0;
             }
             if (failed) {

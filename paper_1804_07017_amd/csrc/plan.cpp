@@ -12,6 +12,7 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <cstdlib>
 
 namespace lu {
 
@@ -59,14 +60,27 @@ bool conflicts(const Access& e, const Access& l) {
 
 }  // namespace
 
+// Trailing size at or below which panels are at most 256 wide (the middle
+// tier of the taper; 0: no middle tier).  LU_TAPER_MID overrides it.
+int taper_mid(int prec) {
+    static const int env = [] {
+        const char* e = std::getenv("LU_TAPER_MID");
+        return (e && *e) ? std::atoi(e) : -1;
+    }();
+    if (env >= 0) return env;
+    return prec == 0 ? kTaperMid64 : kTaperMid32;
+}
+
 int taper_width(int prec, int trailing) {
     // Early termination, done statically: the panel narrows as the trailing
     // matrix shrinks, so that in the tail the factorization of the next panel
     // stays short next to the update it overlaps.  The widths are the block
     // sizes that are fastest for a whole factorization of that size on this
     // GPU (the schedule sweep), per precision class.
-    if (prec == 0) return trailing <= 12288 ? 128 : 1 << 30;      // FP64
-    return trailing <= 16384 ? 128 : 1 << 30;                     // FP32 and mixed
+    const int t128 = prec == 0 ? 12288 : 16384;
+    if (trailing <= t128) return 128;
+    if (trailing <= taper_mid(prec)) return 256;
+    return 1 << 30;
 }
 
 std::vector<int> panel_starts(int n, int b, int taper, int prec) {

@@ -21,6 +21,10 @@ struct PlanTask {
 // of panel j is min(b, taper_width(prec, n - starts[j])).
 std::vector<int> panel_starts(int n, int b, int taper, int prec);
 int taper_width(int prec, int trailing);
+// middle tier of the taper: panels at most 256 wide while the trailing size is
+// in (the 128 threshold, taper_mid]; 0 = none
+constexpr int kTaperMid64 = 0, kTaperMid32 = 0;
+int taper_mid(int prec);
 
 int build_plan(int n, int b, int depth, std::vector<PlanTask>& out);
 // swaps: 0 no left interchanges (a factorization without row interchanges),

@@ -76,7 +76,8 @@ def _square_with_panel(m, w, seed):
 
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("m,w,wgs", [(64, 64, 1), (700, 16, 4), (1000, 64, 8), (1000, 100, 3),
-                                     (2500, 256, 16), (300, 33, 2), (4096, 512, 8)])
+                                     (2500, 256, 16), (300, 33, 2), (4096, 512, 8),
+                                     (1000, 128, 1), (512, 256, 1), (257, 33, 1), (1024, 512, 1)])
 def test_panel_matches_oracle(gpu, prec, m, w, wgs):
     import torch
     A, _ = _square_with_panel(m, w, seed=m + w)
