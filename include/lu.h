@@ -126,6 +126,23 @@ int lu_solve(int n, int nrhs, const double* LU, const int* ipiv, double* B);
 int lu_solve_ex(int n, int nrhs, const double* LU, int lda, const int* ipiv,
                 double* B, int ldb, hipStream_t stream);
 
+/* lu_solve_ex for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and result, with the scratch memory (interchange lists,
+ * ready flags, error word; 1 053 952 bytes) in one statically allocated device
+ * array per GPU instead of library-allocated buffers.  Calls no hipMalloc,
+ * hipFree or other allocating routine and creates no stream or event; the
+ * array's address is looked up once per device, on the first call with that
+ * device current.  Every call on one GPU shares its array: calls on that GPU
+ * that overlap in time (on different streams, or from several host threads)
+ * race and must be serialised by the caller.  Arguments, errors and stream
+ * semantics as lu_solve_ex, plus LU_ERR_UNSUPPORTED when n > LU_NOALLOC_MAX_N.
+ * As with lu_solve_ex, a wait of the triangular solves that times out is not
+ * reported. */
+#define LU_NOALLOC_MAX_N 65536
+int lu_solve_noalloc(int n, int nrhs, const double* LU, int lda, const int* ipiv,
+                     double* B, int ldb, hipStream_t stream);
+
 /* Mixed-precision solve with FP64 iterative refinement (not in the paper;
  * the precision axis of this library).  A (FP64) and B are read, never
  * written; X receives the solution.  The LU of a working copy of A is

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "liblu_mi355x.so")
 
 LU_FP64, LU_FP32, LU_MIXED_FP16, LU_MIXED_BF16 = 0, 1, 2, 3
 LU_ERR_HIP, LU_ERR_BARRIER, LU_ERR_NOMEM, LU_ERR_UNSUPPORTED, LU_ERR_NONFINITE = -100, -101, -102, -103, -104
+LU_NOALLOC_MAX_N = 65536
 LU_ERR_SINGULAR = -105
 LU_IR_OK, LU_IR_FELL_BACK, LU_IR_RESID_HIGH = 0, 1, 2
 LU_TASK_PANEL, LU_TASK_UPDATE, LU_TASK_LSWAP, LU_TASK_LPERM = 0, 1, 2, 3
@@ -48,6 +49,7 @@ _SIGS = {
     "lu_schedule_default": (_I, [_I, _I, ctypes.POINTER(Schedule)]),
     "lu_solve": (_I, [_I, _I, _P, _P, _P]),
     "lu_solve_ex": (_I, [_I, _I, _P, _I, _P, _P, _I, _P]),
+    "lu_solve_noalloc": (_I, [_I, _I, _P, _I, _P, _P, _I, _P]),
     "lu_solve_ir": (_I, [_I, _I, _P, _I, _P, _I, _P, _I, _I, _I, ctypes.POINTER(_I),
                          ctypes.POINTER(ctypes.c_double), _P]),
     "lu_selector_load": (_I, [ctypes.c_char_p]),
@@ -239,6 +241,13 @@ def lu_solve_ex(LU, ipiv, B, stream=None):
     n = LU.shape[0]
     nrhs = 1 if B.dim() == 1 else B.shape[1]
     return load().lu_solve_ex(n, nrhs, _ptr(LU), _ld(LU), _ptr(ipiv), _ptr(B), _ld(B), _stream(stream))
+
+
+def lu_solve_noalloc(LU, ipiv, B, stream=None):
+    """lu_solve_ex with statically allocated scratch memory (no allocation)."""
+    n = LU.shape[0]
+    nrhs = 1 if B.dim() == 1 else B.shape[1]
+    return load().lu_solve_noalloc(n, nrhs, _ptr(LU), _ld(LU), _ptr(ipiv), _ptr(B), _ld(B), _stream(stream))
 
 
 def lu_solve_ir(A, B, X, prec=LU_MIXED_FP16, max_iter=10, stream=None):

@@ -20,7 +20,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CLANG = "/opt/rocm/llvm/bin/clang++"
 ARCH = "gfx950"
 
-SOURCES = ["panel.hip", "update.hip", "gemm.hip", "solve.hip", "mlp.hip", "chol.hip", "qr.hip", "band.hip",
+SOURCES = ["panel.hip", "update.hip", "gemm.hip", "solve.hip", "mlp.hip", "chol.hip", "qr.hip", "band.hip", "noalloc.hip",
            "plan.cpp", "api.cpp", "solve_api.cpp", "selector.cpp", "chol_api.cpp", "qr_api.cpp", "band_api.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",

@@ -186,6 +186,7 @@ int launch_trsv_chol(const T* L, long long lda, int n, T* x, int* flags, int epo
 template <typename T>
 int launch_trsv_upper(const T* LU, long long lda, int n, T* x, int* flags, int epoch, unsigned* err,
                       long long spin_limit, hipStream_t stream);
+constexpr int kTrsvRows = 64;     // rows per block of the blocked triangular solves (one ready flag each)
 int trsv_block_rows();
 
 // IR building blocks (FP64 residual side)

@@ -15,7 +15,7 @@ namespace lu {
 
 namespace {
 
-constexpr int kRB = 64;          // rows per triangular block
+constexpr int kRB = kTrsvRows;   // rows per triangular block
 constexpr int kThreads = 256;    // 4 column groups x 64 rows
 
 // Wait until a block's ready flag shows `epoch` (relaxed device-scope polls;
