@@ -243,11 +243,21 @@ def _device_residual(gpu, dA0, dLU, ipiv):
 @pytest.mark.parametrize("b,depth,cus,taper", [(256, 1, 16, -1), (512, 2, 8, -1), (256, 2, 32, 1)])
 def test_uniform_32768_schedules(gpu, b, depth, cus, taper):
     """Full-size FP64 look-ahead LU: scaled residual with a library GEMM, the
-    pivots are a legal permutation, every multiplier is bounded by 1, and the
-    first panel's pivots equal the oracle's (a plain column search over A)."""
+    pivots are a legal permutation, every multiplier is bounded by 1, the
+    first pivot is the plain column search over A, and the whole pivot
+    sequence equals the oracle's (tests/golden/xo_uniform_n32768_s1.json holds
+    the SHA-256 of the oracle's 32768 pivots for this seeded matrix; rounding
+    differences could only change a pivot at a near-tie, which this matrix
+    does not have)."""
+    import hashlib
+    import json
     import torch
+    from tests.golden import make_xo
     n = 32768
+    with open(make_xo.paths("uniform", n, 1)[1]) as f:
+        meta = json.load(f)
     A = synth.uniform(n, seed=1)
+    assert make_xo.check_fingerprint(A, meta["fingerprint"]), "regenerated matrix differs"
     dA0 = gpu.to_device(A)
     a00 = A[:, 0].copy()
     del A
@@ -259,6 +269,7 @@ def test_uniform_32768_schedules(gpu, b, depth, cus, taper):
     ip = ipiv.cpu().numpy()
     assert (ip >= np.arange(n)).all() and (ip < n).all()
     assert ip[0] == int(np.argmax(np.abs(a00)))
+    assert hashlib.sha256(ip.astype(np.int32).tobytes()).hexdigest() == meta["ipiv_sha256"]
     assert torch.tril(dA, -1).abs().max().item() <= 1.0
     rf = _device_residual(gpu, dA0, dA, ip)
     assert rf <= 16.0, rf

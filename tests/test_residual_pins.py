@@ -75,3 +75,21 @@ def test_r_chol_hand_value():
     F = np.array([[2.0, 99.0], [1.0, 2.0 + D]], order="F")
     got = oracle.r_chol(A, F)
     assert got == pytest.approx(2.0 ** 14 / 7.0, rel=1e-15)
+
+
+def test_kappa_estimate_matches_exact_condition_number():
+    """The Hager estimate used as the yardstick of the full-size FP32
+    refinement test, on small matrices where kappa_inf is computed exactly:
+    never above it, and within the factor 3 the test allows."""
+    import torch
+    from tests.test_gpu_ir import _kappa_inf_estimate
+    rng = np.random.default_rng(3)
+    for n in (50, 200, 400):
+        for scale in (None, 1e-3):
+            A = rng.uniform(-1, 1, (n, n))
+            if scale is not None:
+                A[:, 0] *= scale                       # ill-conditioned by a column scaling
+            exact = np.linalg.norm(A, np.inf) * np.linalg.norm(np.linalg.inv(A), np.inf)
+            est = _kappa_inf_estimate(torch.from_numpy(A))
+            assert est <= exact * (1 + 1e-10)
+            assert est >= exact / 3.0, (n, scale, est, exact)
