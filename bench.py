@@ -69,12 +69,12 @@ def gemm_algorithmic_bytes(lu, n, b, depth, taper):
     return tot / max(cnt, 1)
 
 
-def oracle_solution(n, seed=1):
-    """The oracle's FP64 solution of the seeded row-dominant system of size n,
-    as written by tests/golden/make_xo.py (float64[n]), with its metadata, or
-    (None, None) when none is stored for n."""
+def oracle_solution(n, workload="dominant", seed=1):
+    """The oracle's FP64 solution of the seeded system of size n (workload
+    "dominant" or "uniform"), as written by tests/golden/make_xo.py
+    (float64[n]), with its metadata, or (None, None) when none is stored for n."""
     import numpy as np
-    stem = os.path.join(ROOT, "tests", "golden", "xo_dominant_n%d_s%d" % (n, seed))
+    stem = os.path.join(ROOT, "tests", "golden", "xo_%s_n%d_s%d" % (workload, n, seed))
     if not (os.path.exists(stem + ".npy") and os.path.exists(stem + ".json")):
         return None, None
     with open(stem + ".json") as f:
@@ -349,10 +349,16 @@ def main():
     g = torch.Generator(device=dev)
     g.manual_seed(1)
     print("bench: generating n=%d inputs" % n, file=sys.stderr, flush=True)
-    A0 = lu.colmajor(n)
-    A0.uniform_(-1.0, 1.0, generator=g)
+    # the uniform[-1,1) system from the host generators (seed 1): the one the
+    # oracle's stored solution and pivot hash belong to
+    xo_u, meta_u = oracle_solution(n, "uniform")
+    Ah = synth.uniform(n, seed=1)
+    if xo_u is not None and not same_matrix(Ah, meta_u["fingerprint"]):
+        raise RuntimeError("the regenerated uniform matrix differs from the oracle's")
+    A0 = lu.to_device(Ah)
+    del Ah
     A = lu.colmajor(n)
-    bvec = torch.empty(n, dtype=torch.float64, device=dev).uniform_(-1.0, 1.0, generator=g)
+    bvec = torch.from_numpy(synth.rhs(n, seed=1)[:, 0].copy()).to(dev)
     x = torch.empty(n, dtype=torch.float64, device=dev)
     ipiv = torch.zeros(n, dtype=torch.int32, device=dev)
     D = None
@@ -360,7 +366,7 @@ def main():
     if not args.no_ir:
         # the row-dominant system from the host generators (seed 1): the one
         # the oracle's stored solution belongs to
-        xo, meta = oracle_solution(n)
+        xo, meta = oracle_solution(n, "dominant")
         Dh = synth.dominant(n, seed=1)
         if xo is not None and not same_matrix(Dh, meta["fingerprint"]):
             raise RuntimeError("the regenerated row-dominant matrix differs from the oracle's")
@@ -444,6 +450,12 @@ def main():
     if xo is not None:
         xs = X.cpu().numpy()
         err_vs_oracle = float(np.abs(xs - xo).max() / np.abs(xo).max())
+    err64_vs_oracle = pivots_match = None
+    if xo_u is not None:
+        import hashlib
+        err64_vs_oracle = float(np.abs(x.cpu().numpy() - xo_u).max() / np.abs(xo_u).max())
+        pivots_match = hashlib.sha256(ipiv.cpu().numpy().astype(np.int32).tobytes()).hexdigest() == \
+            meta_u["ipiv_sha256"]
 
     # untimed passes for the rooflines: the per-launch GEMM timing hook records
     # events around every trailing-GEMM launch of one FP64 factorization and of
@@ -495,12 +507,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "FP64 look-ahead LU + 1-RHS solve of a uniform[-1,1) n=%d matrix; mixed FP16 LU "
-                               "+ FP64 refinement on the row-dominant n=%d matrix" % (n, n),
+        "config": {"workload": "FP64 look-ahead LU + 1-RHS solve of the seeded uniform[-1,1) n=%d matrix; mixed "
+                               "FP16 LU + FP64 refinement on the seeded row-dominant n=%d matrix" % (n, n),
                    "n": n, "b": used[0], "depth": used[1], "panel_cus": used[2], "taper": taper_on},
         "fp64": {"t_factor_ms": round(t_fact, 3), "t_solve_ms": round(t_solve, 3),
                  "tts_ms": round(t_fact + t_solve, 3), "pct_fp64_peak": round(100 * gflops / 1e3 / FP64_PEAK_TFLOPS, 2),
-                 "hpl_resid": hpl},
+                 "hpl_resid": hpl, "err_vs_oracle": err64_vs_oracle, "pivots_match_oracle": pivots_match},
     }
     if D is not None:
         irs = [r[2] for r in recs]
