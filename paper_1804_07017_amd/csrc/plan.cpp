@@ -71,13 +71,24 @@ int taper_mid(int prec) {
     return prec == 0 ? kTaperMid64 : kTaperMid32;
 }
 
+// Trailing size at or below which panels are 128 wide; LU_TAPER_NARROW
+// overrides it for every precision.
+int taper_narrow(int prec) {
+    static const int env = [] {
+        const char* e = std::getenv("LU_TAPER_NARROW");
+        return (e && *e) ? std::atoi(e) : -1;
+    }();
+    if (env >= 0) return env;
+    return prec == 0 ? kTaperNarrow64 : kTaperNarrow32;
+}
+
 int taper_width(int prec, int trailing) {
     // Early termination, done statically: the panel narrows as the trailing
     // matrix shrinks, so that in the tail the factorization of the next panel
     // stays short next to the update it overlaps.  The widths are the block
     // sizes that are fastest for a whole factorization of that size on this
     // GPU (the schedule sweep), per precision class.
-    const int t128 = prec == 0 ? 12288 : 16384;
+    const int t128 = taper_narrow(prec);
     if (trailing <= t128) return 128;
     if (trailing <= taper_mid(prec)) return 256;
     return 1 << 30;

@@ -25,6 +25,9 @@ int taper_width(int prec, int trailing);
 // in (the 128 threshold, taper_mid]; 0 = none
 constexpr int kTaperMid64 = 0, kTaperMid32 = 0;
 int taper_mid(int prec);
+// trailing size at or below which panels are 128 wide: FP64, FP32 and mixed
+constexpr int kTaperNarrow64 = 12288, kTaperNarrow32 = 16384;
+int taper_narrow(int prec);
 
 int build_plan(int n, int b, int depth, std::vector<PlanTask>& out);
 // swaps: 0 no left interchanges (a factorization without row interchanges),
