@@ -36,6 +36,27 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 if os.path.dirname(HERE) not in sys.path:
     sys.path.insert(0, os.path.dirname(HERE))
 
+# The library sources that decide how long lu_factor_ex takes (kernels of the
+# factorization, its scheduler and the panel boundaries).  A sweep records their
+# hash; timings taken with other sources describe another library.
+TIMED_SOURCES = ("panel.hip", "update.hip", "gemm.hip", "api.cpp", "plan.cpp", "plan.hpp", "kernels.hpp",
+                 "common.hpp", "moves.hpp", "mfma.hpp", "state.hpp")
+# environment settings that change the schedule or the kernels' launch shapes
+SCHEDULE_ENV = ("LU_B", "LU_DEPTH", "LU_PANEL_CUS", "LU_TAPER", "LU_TAPER_MID", "LU_TAPER_NARROW", "LU_WIDE_ROWS",
+                "LU_PANEL_OCC", "LU_PANEL_XCD", "LU_ISLAND")
+
+
+def build_identity():
+    """Hash (first 16 hex digits of SHA-256) of TIMED_SOURCES, in that order,
+    and the taper setting the sweep runs with (the library default: on)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in TIMED_SOURCES:
+        with open(os.path.join(HERE, "csrc", name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return {"lu_sources_sha256_16": h.hexdigest()[:16], "sources": list(TIMED_SOURCES), "taper": 1}
+
+
 B_CHOICES = (64, 128, 256, 512)
 DEPTH_CHOICES = (0, 1, 2)
 CU_CHOICES = (8, 16, 32)
@@ -59,15 +80,37 @@ def labels(sched):
     return [B_CHOICES.index(b), DEPTH_CHOICES.index(d), CU_CHOICES.index(p)]
 
 
-def sweep(sizes, precs, reps, out, seed=1):
+METHOD = ("median of lu_factor_ex runs timed with HIP events on the factorization's stream after one warm-up run "
+          "per size and precision; uniform[-1,1) matrices from torch's device generator, seed 1; default taper; "
+          "{train} runs per point at the training sizes, {held} at the held-out sizes")
+
+
+def sweep(sizes, precs, reps, out, seed=1, role="train"):
     import torch
     import paper_1804_07017_amd as lu
     lu.load()
     torch.cuda.set_device(0)
-    table = {"device": torch.cuda.get_device_name(0), "reps": reps, "entries": []}
+    set_env = [k for k in SCHEDULE_ENV if os.environ.get(k)]
+    if set_env:
+        raise RuntimeError("schedule settings in the environment (%s): the sweep times the defaults" % set_env)
+    ident = build_identity()
+    table = {"device": torch.cuda.get_device_name(0), "reps": reps, "build": ident, "entries": []}
     if os.path.exists(out):
         with open(out) as f:
             table = json.load(f)
+        if table.get("build") != ident:
+            raise RuntimeError("%s was swept with other library sources or taper (%s), not %s" %
+                               (out, table.get("build"), ident))
+    key = "train_sizes" if role == "train" else "heldout_sizes"
+    table.setdefault("train_sizes", [])
+    table.setdefault("heldout_sizes", [])
+    table.setdefault("runs", {})
+    table["runs"][role] = reps
+    for n in sizes:
+        if n not in table[key]:
+            table[key].append(n)
+    table[key].sort()
+    table["method"] = METHOD.format(train=table["runs"].get("train", "?"), held=table["runs"].get("heldout", "?"))
     done = {(e["n"], e["prec"], e["b"], e["depth"], e["panel_cus"]) for e in table["entries"]}
     stream = torch.cuda.Stream()
     for prec in precs:
@@ -185,6 +228,8 @@ def main(argv=None):
     s.add_argument("--precs", default="0,1,2")
     s.add_argument("--reps", type=int, default=3)
     s.add_argument("--out", required=True)
+    s.add_argument("--role", choices=("train", "heldout"), default="train",
+                   help="list the sizes among the training or the held-out sizes of the table")
     t = sub.add_parser("train")
     t.add_argument("--sweep", required=True, help="comma-separated sweep JSON files")
     t.add_argument("--sizes", default="", help="training sizes (default: every complete size)")
@@ -200,7 +245,7 @@ def main(argv=None):
     ints = lambda txt: [int(v) for v in txt.split(",") if v]
     if a.cmd == "sweep":
         t0 = time.time()
-        sweep(ints(a.sizes), ints(a.precs), a.reps, a.out)
+        sweep(ints(a.sizes), ints(a.precs), a.reps, a.out, role=a.role)
         print("sweep done in %.1f s" % (time.time() - t0), flush=True)
     elif a.cmd == "train":
         train(a.sweep.split(","), set(ints(a.sizes)), a.out, a.epochs, a.lr, a.seed)
