@@ -24,6 +24,13 @@
 // Every element receives its updates in the order of the unblocked algorithm
 // (column k = 0, 1, ... of the whole matrix), each as a separate multiply and
 // subtract, so the panel's result does not depend on P.
+//
+// Every access to the panel is a relaxed device-scope atomic (common.hpp:
+// it bypasses the per-CU and per-XCD caches), and the barriers drain and
+// count without cache write-back or invalidate, as in the LU panel: at device
+// scope those act on a whole XCD's L2 and stall the update running beside the
+// panel, and they left plain stores of one work-group in its XCD's L2 until
+// another work-group's maintenance ran.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -47,8 +54,10 @@ __global__ __launch_bounds__(kCholThreads) void chol_panel_kernel(CholPanelArgs<
     const int m = a.m, w = a.w;
     const long long lda = a.lda;
     T* __restrict__ A = a.A;
+    constexpr int S = __HIP_MEMORY_SCOPE_AGENT;
     unsigned epoch = 0;
-    if (g == 0 && tid == 0 && a.sync_next) a.sync_next[0] = 0u;   // the next launch's barrier counter
+    // the next launch's barrier counter (its previous user has finished)
+    if (g == 0 && tid == 0 && a.sync_next) xstore_s<S>(a.sync_next, 0u);
     const int stride = kCholThreads * P;
     constexpr int kChunk = kChunkCols;                      // columns per pass of the in-panel update
     constexpr bool kPrefetch = kCholRows <= 2;              // registers for a second chunk
@@ -58,7 +67,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_panel_kernel(CholPanelArgs<
         // 1. the diagonal part, factored in LDS by wave 0
         for (int e = tid; e < kCholNB * kCholNB; e += kCholThreads) {
             const int r = e % kCholNB, c = e / kCholNB;
-            D[r][c] = (r < nbw && c <= r) ? A[(cb + r) + (long long)(cb + c) * lda] : T(0);
+            D[r][c] = (r < nbw && c <= r) ? cload<S>(A + (cb + r) + (long long)(cb + c) * lda) : T(0);
         }
         if (tid == 0) s_bad = 0;
         __syncthreads();
@@ -95,7 +104,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_panel_kernel(CholPanelArgs<
             const int ic = min(i, m - 1);              // clamped: unconditional loads
 #pragma unroll
             for (int c = 0; c < kCholNB; ++c) {
-                const T v = A[ic + (long long)(cb + min(c, nbw - 1)) * lda];
+                const T v = cload<S>(A + ic + (long long)(cb + min(c, nbw - 1)) * lda);
                 x[r][c] = (i < m && c < nbw) ? v : T(0);
             }
         }
@@ -119,16 +128,16 @@ __global__ __launch_bounds__(kCholThreads) void chol_panel_kernel(CholPanelArgs<
             if (i < m) {
 #pragma unroll
                 for (int c = 0; c < kCholNB; ++c)
-                    if (c < nbw) A[i + (long long)(cb + c) * lda] = x[r][c];
+                    if (c < nbw) cstore<S>(A + i + (long long)(cb + c) * lda, x[r][c]);
             }
         }
         // every group has read the diagonal part (step 1) before group 0
         // overwrites it with the factor
-        if (grid_barrier(a.sync, a.sync + 1, ++epoch, a.spin_limit)) return;
+        if (grid_barrier_nofence(a.sync, a.sync + 1, ++epoch, a.spin_limit, P)) return;
         if (g == 0) {
             for (int e = tid; e < kCholNB * kCholNB; e += kCholThreads) {
                 const int r = e % kCholNB, c = e / kCholNB;
-                if (r < nbw && c <= r) A[(cb + r) + (long long)(cb + c) * lda] = D[r][c];
+                if (r < nbw && c <= r) cstore<S>(A + (cb + r) + (long long)(cb + c) * lda, D[r][c]);
             }
             if (tid == 0 && s_bad != 0 && a.info) atomicCAS(a.info, 0, a.info_col_base + cb + s_bad);
         }
@@ -139,7 +148,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_panel_kernel(CholPanelArgs<
             const int wr = (w - right0 + kChunk - 1) / kChunk * kChunk;     // zero past w: whole chunks
             for (int e = tid; e < wr * kCholNB; e += kCholThreads) {
                 const int c = e % wr, k = e / wr;
-                UtT[k][c] = (k < nbw && right0 + c < w) ? A[(right0 + c) + (long long)(cb + k) * lda] : T(0);
+                UtT[k][c] = (k < nbw && right0 + c < w) ? cload<S>(A + (right0 + c) + (long long)(cb + k) * lda) : T(0);
             }
         }
         __syncthreads();
@@ -150,7 +159,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_panel_kernel(CholPanelArgs<
 #pragma unroll
                 for (int cc = 0; cc < kChunk; ++cc) {
                     const int c = c0 + cc;
-                    v[r][cc] = (i < m && c < w && c <= i) ? A[i + (long long)c * lda] : T(0);
+                    v[r][cc] = (i < m && c < w && c <= i) ? cload<S>(A + i + (long long)c * lda) : T(0);
                 }
             }
         };
@@ -175,7 +184,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_panel_kernel(CholPanelArgs<
 #pragma unroll
                 for (int cc = 0; cc < kChunk; ++cc) {
                     const int c = c0 + cc;
-                    if (i < m && c < w && c <= i) A[i + (long long)c * lda] = v[r][cc];
+                    if (i < m && c < w && c <= i) cstore<S>(A + i + (long long)c * lda, v[r][cc]);
                 }
             }
             if (c0 + kChunk < w) {
@@ -186,7 +195,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_panel_kernel(CholPanelArgs<
                     for (int cc = 0; cc < kChunk; ++cc) v[r][cc] = vn[r][cc];
             }
         }
-        if (grid_barrier(a.sync, a.sync + 1, ++epoch, a.spin_limit)) return;
+        if (grid_barrier_nofence(a.sync, a.sync + 1, ++epoch, a.spin_limit, P)) return;
     }
 }
 
