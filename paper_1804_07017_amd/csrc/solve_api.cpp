@@ -218,16 +218,22 @@ int solve_ir_impl(int n, int nrhs, const double* A, int lda, const double* B, in
         double* x = X + (long long)c * ldx;
         double* r = reinterpret_cast<double*>(s->ir_r.ptr);
         if (launch_fill_zero(x, (size_t)n * sizeof(double), stream)) return LU_ERR_HIP;
+        double bn;
+        if ((rc = dev_amax(s, b, n, stream, &bn))) return rc;
         double prev = INFINITY;
         int it = 0;
         for (;; ++it) {
-            double res;
-            if ((rc = hpl_resid(s, n, A, lda, b, x, anorm, stream, &res))) return rc;   // leaves r = b - A x
-            if (std::isnan(res)) { converged = false; break; }
-            if (res <= 16.0) { worst = std::max(worst, res); break; }
-            if (it >= max_iter || (it >= 2 && res >= prev)) { converged = false; break; }
-            prev = res;
-            if (launch_convert_f64_f32(r, n, d32, n, n, 1, stream)) return LU_ERR_HIP;
+            // x = 0 at the start: r = b needs no product, and only b = 0 passes the test
+            const bool start = it == 0 && bn > 0.0;
+            if (!start) {
+                double res;
+                if ((rc = hpl_resid(s, n, A, lda, b, x, anorm, stream, &res))) return rc;   // leaves r = b - A x
+                if (std::isnan(res)) { converged = false; break; }
+                if (res <= 16.0) { worst = std::max(worst, res); break; }
+                if (it >= max_iter || (it >= 2 && res >= prev)) { converged = false; break; }
+                prev = res;
+            }
+            if (launch_convert_f64_f32(start ? b : r, n, d32, n, n, 1, stream)) return LU_ERR_HIP;
             if ((rc = solve_with_factor<float>(s, n, 1, A32, n, ipiv, d32, n, stream, moves_ready))) return rc;
             moves_ready = true;
             if (launch_axpy_f32_to_f64(x, d32, n, stream)) return LU_ERR_HIP;
