@@ -40,6 +40,16 @@ def choose(theta, n, prec):
     return tune.B_CHOICES[pr[0]], tune.DEPTH_CHOICES[pr[1]], tune.CU_CHOICES[pr[2]]
 
 
+def test_sweep_matches_the_library_sources():
+    """The sweep was timed with the factorization sources and the taper
+    setting of this tree; after a change to any of them the timings describe
+    another library, and the sweep (and the training) must be redone."""
+    d, _ = sweep()
+    assert d.get("build") == tune.build_identity(), (
+        "selector_sweep_mi355x.json was taken with %s; the tree has %s: re-run tune.py sweep/train"
+        % (d.get("build"), tune.build_identity()))
+
+
 def test_sweep_is_exhaustive_on_every_size():
     d, tab = sweep()
     for n in d["train_sizes"] + d["heldout_sizes"]:
