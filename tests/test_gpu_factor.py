@@ -276,6 +276,42 @@ def test_uniform_32768_schedules(gpu, b, depth, cus, taper):
 
 
 @pytest.mark.timeout(900)
+def test_uniform_40000_per_step_left_swaps(gpu):
+    """Past 32768 rows per column segment the left interchanges run as one
+    LSWAP task per step instead of the deferred permutation, and panels taller
+    than 32768 rows use 1024 rows per work-group: n = 40000 with the tapered
+    b = 256 schedule at depth 2 (ragged last panel).  The factorization is
+    checked by its scaled residual, legal pivots, bounded multipliers and the
+    first pivot, and against the conventional loop (depth 0) of the same
+    block size: the same factors and pivots bit for bit, since the look-ahead
+    reorders operations only."""
+    import torch
+    n = 40000
+    A = synth.uniform(n, seed=5)
+    dA0 = gpu.to_device(A)
+    a00 = A[:, 0].copy()
+    del A
+    results = []
+    for depth in (2, 0):
+        dA = dA0.clone()
+        ipiv = torch.zeros(n, dtype=torch.int32, device="cuda")
+        print("n=40000 depth %d" % depth, flush=True)
+        assert gpu.lu_factor_ex(dA, ipiv, sched=(256, depth, 32, 1)) == 0
+        torch.cuda.synchronize()
+        assert gpu.lu_factor_info() == (0, 0)
+        results.append((dA, ipiv.cpu().numpy()))
+    (dA, ip), (dB, ipb) = results
+    assert np.array_equal(ip, ipb)
+    assert torch.equal(dA, dB)
+    del dB
+    assert (ip >= np.arange(n)).all() and (ip < n).all()
+    assert ip[0] == int(np.argmax(np.abs(a00)))
+    assert torch.tril(dA, -1).abs().max().item() <= 1.0
+    rf = _device_residual(gpu, dA0, dA, ip)
+    assert rf <= 16.0, rf
+
+
+@pytest.mark.timeout(900)
 def test_planted_factors_32768(gpu):
     """A = P L U with L scaled to a = 0.1 sqrt(1024/n) (||L^-1|| as at n=1024):
     the pivots and both factors are recovered."""
