@@ -58,6 +58,8 @@ __global__ __launch_bounds__(kThreads) void trsv_lower_unit_kernel(const T* __re
     const int tid = threadIdx.x, i = tid % kRB, g = tid / kRB;
     const int row = r * kRB + i;
     const int nb = min(kRB, n - r * kRB);
+    // this block's right-hand side, loaded before any wait (nothing else writes it)
+    const T b_row = (tid < kRB && row < n) ? x[row] : T(0);
     // the diagonal block does not depend on other blocks: stage it first
     for (int s = g; s < kRB; s += 4) Ld[s][i] = (row < n && s < nb) ? LU[row + (long long)(r * kRB + s) * lda] : T(0);
     // this thread's slice of block (r, cb) of L: loaded one block ahead, before
@@ -89,7 +91,7 @@ __global__ __launch_bounds__(kThreads) void trsv_lower_unit_kernel(const T* __re
     __syncthreads();
     T y = T(0);
     if (tid < kRB) {
-        y = (row < n) ? x[row] - ((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) : T(0);
+        y = (row < n) ? b_row - ((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) : T(0);
         for (int s = 0; s < nb; ++s) {
             const T xs = lane_t(y, s);                 // lane s's value (s is uniform)
             if (i > s) y -= Ld[s][i] * xs;
@@ -109,6 +111,8 @@ __global__ __launch_bounds__(kThreads) void trsv_upper_kernel(const T* __restric
     const int tid = threadIdx.x, i = tid % kRB, g = tid / kRB;
     const int row = r * kRB + i;
     const int nb = min(kRB, n - r * kRB);
+    // this block's right-hand side, loaded before any wait (nothing else writes it)
+    const T b_row = (tid < kRB && row < n) ? x[row] : T(0);
     for (int s = g; s < kRB; s += 4) Ud[s][i] = (row < n && s < nb) ? LU[row + (long long)(r * kRB + s) * lda] : T(0);
     // block (r, cb) of U loaded one block ahead of the wait (as in the lower
     // solve); columns past n (only in the last block) contribute zero
@@ -144,7 +148,7 @@ __global__ __launch_bounds__(kThreads) void trsv_upper_kernel(const T* __restric
     __syncthreads();
     T y = T(0);
     if (tid < kRB) {
-        y = (row < n) ? x[row] - ((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) : T(0);
+        y = (row < n) ? b_row - ((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) : T(0);
         if constexpr (sizeof(T) == 4) {
             // FP32 (the working precision of the refinement's corrections): the
             // diagonal's reciprocal is formed before the serial chain, which then
@@ -178,6 +182,8 @@ __global__ __launch_bounds__(kThreads) void trsv_chol_lower_kernel(const T* __re
     const int tid = threadIdx.x, i = tid % kRB, g = tid / kRB;
     const int row = r * kRB + i;
     const int nb = min(kRB, n - r * kRB);
+    // this block's right-hand side, loaded before any wait (nothing else writes it)
+    const T b_row = (tid < kRB && row < n) ? x[row] : T(0);
     for (int s = g; s < kRB; s += 4) Ld[s][i] = (row < n && s < nb) ? L[row + (long long)(r * kRB + s) * lda] : T(0);
     constexpr int kPerT = kRB / 4;
     auto load_l = [&](int cb, T (&lv)[kPerT]) {
@@ -206,7 +212,7 @@ __global__ __launch_bounds__(kThreads) void trsv_chol_lower_kernel(const T* __re
     __syncthreads();
     T y = T(0);
     if (tid < kRB) {
-        y = (row < n) ? x[row] - ((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) : T(0);
+        y = (row < n) ? b_row - ((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) : T(0);
         for (int s = 0; s < nb; ++s) {
             if (i == s) y = y / Ld[s][i];
             const T xs = lane_t(y, s);                 // lane s's value (s is uniform)
@@ -231,6 +237,8 @@ __global__ __launch_bounds__(kThreads) void trsv_chol_upper_kernel(const T* __re
     const int r0 = r * kRB;
     const int row = r0 + i;
     const int nb = min(kRB, n - r0);
+    // this block's right-hand side, loaded before any wait (nothing else writes it)
+    const T b_row = (tid < kRB && row < n) ? x[row] : T(0);
     // coalesced along the rows of L: thread (jj = tid % 64) reads L(r0 + jj, r0 + ii)
     for (int ii = g; ii < kRB; ii += 4) {
         const bool ok = i < nb && ii < nb && i >= ii;
@@ -272,7 +280,7 @@ __global__ __launch_bounds__(kThreads) void trsv_chol_upper_kernel(const T* __re
     __syncthreads();
     T y = T(0);
     if (tid < kRB) {
-        y = (row < n) ? x[row] - ((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) : T(0);
+        y = (row < n) ? b_row - ((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) : T(0);
         for (int s = nb - 1; s >= 0; --s) {
             if (i == s) y = y / Ud[s][i];
             const T xs = lane_t(y, s);
