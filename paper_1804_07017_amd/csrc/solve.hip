@@ -92,9 +92,15 @@ __global__ __launch_bounds__(kThreads) void trsv_lower_unit_kernel(const T* __re
     T y = T(0);
     if (tid < kRB) {
         y = (row < n) ? b_row - ((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) : T(0);
-        for (int s = 0; s < nb; ++s) {
+        // unrolled and branch-free, so that the LDS reads (independent of y)
+        // issue ahead of the serial chain instead of one round trip per step;
+        // columns past nb are zero and lanes past nb hold 0, so they change
+        // nothing
+#pragma unroll
+        for (int s = 0; s < kRB; ++s) {
+            const T l = Ld[s][i];
             const T xs = lane_t(y, s);                 // lane s's value (s is uniform)
-            if (i > s) y -= Ld[s][i] * xs;
+            y = (i > s) ? y - l * xs : y;
         }
     }
     publish(x, row, y, tid < kRB && row < n, &flags[r], epoch);
@@ -149,21 +155,29 @@ __global__ __launch_bounds__(kThreads) void trsv_upper_kernel(const T* __restric
     T y = T(0);
     if (tid < kRB) {
         y = (row < n) ? b_row - ((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) : T(0);
+        // branch-free, so that the LDS reads (independent of y) issue ahead of
+        // the serial chain instead of one round trip per step
         if constexpr (sizeof(T) == 4) {
             // FP32 (the working precision of the refinement's corrections): the
             // diagonal's reciprocal is formed before the serial chain, which then
             // multiplies (within 1.5 ulp of the division)
             const T rd = (i < nb) ? T(1) / Ud[i][i] : T(0);
-            for (int s = nb - 1; s >= 0; --s) {
-                if (i == s) y = y * rd;
+#pragma unroll
+            for (int s = kRB - 1; s >= 0; --s) {
+                const bool live = s < nb;                  // steps past a ragged block's end change nothing
+                const T u = Ud[s][i];
+                y = (live && i == s) ? y * rd : y;
                 const T xs = lane_t(y, s);             // lane s's value (s is uniform)
-                if (i < s) y -= Ud[s][i] * xs;
+                y = (live && i < s) ? y - u * xs : y;
             }
         } else {
-            for (int s = nb - 1; s >= 0; --s) {
-                if (i == s) y = y / Ud[s][i];
+#pragma unroll
+            for (int s = kRB - 1; s >= 0; --s) {
+                const bool live = s < nb;                  // steps past a ragged block's end change nothing
+                const T u = Ud[s][i];
+                y = (live && i == s) ? y / u : y;          // other lanes' quotients are dropped
                 const T xs = lane_t(y, s);             // lane s's value (s is uniform)
-                if (i < s) y -= Ud[s][i] * xs;
+                y = (live && i < s) ? y - u * xs : y;
             }
         }
     }
