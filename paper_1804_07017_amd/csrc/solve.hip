@@ -227,10 +227,14 @@ __global__ __launch_bounds__(kThreads) void trsv_chol_lower_kernel(const T* __re
     T y = T(0);
     if (tid < kRB) {
         y = (row < n) ? b_row - ((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) : T(0);
-        for (int s = 0; s < nb; ++s) {
-            if (i == s) y = y / Ld[s][i];
+        // unrolled and branch-free (LDS reads ahead of the serial chain)
+#pragma unroll
+        for (int s = 0; s < kRB; ++s) {
+            const bool live = s < nb;                  // steps past a ragged block's end change nothing
+            const T l = Ld[s][i];
+            y = (live && i == s) ? y / l : y;          // other lanes' quotients are dropped
             const T xs = lane_t(y, s);                 // lane s's value (s is uniform)
-            if (i > s) y -= Ld[s][i] * xs;
+            y = (live && i > s) ? y - l * xs : y;
         }
     }
     publish(x, row, y, tid < kRB && row < n, &flags[r], epoch);
@@ -295,10 +299,13 @@ __global__ __launch_bounds__(kThreads) void trsv_chol_upper_kernel(const T* __re
     T y = T(0);
     if (tid < kRB) {
         y = (row < n) ? b_row - ((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) : T(0);
-        for (int s = nb - 1; s >= 0; --s) {
-            if (i == s) y = y / Ud[s][i];
+#pragma unroll
+        for (int s = kRB - 1; s >= 0; --s) {
+            const bool live = s < nb;                  // steps past a ragged block's end change nothing
+            const T u = Ud[s][i];
+            y = (live && i == s) ? y / u : y;          // other lanes' quotients are dropped
             const T xs = lane_t(y, s);
-            if (i < s) y -= Ud[s][i] * xs;
+            y = (live && i < s) ? y - u * xs : y;
         }
     }
     publish(x, row, y, tid < kRB && row < n, &flags[r], epoch);
