@@ -25,7 +25,11 @@ __device__ __forceinline__ bool wait_flag(const int* flag, int epoch, unsigned* 
     if (threadIdx.x == 0) {
         int fail = 0;
         const long long t0 = wall_clock64();
+        unsigned spins = 0;
+        // the error word and the clock every 16th poll: a poll is one round
+        // trip to the coherence point, and a flag usually arrives within a few
         while (xload(flag) != epoch) {
+            if ((++spins & 15u) != 0u) continue;
             if (xload(err) != 0u) { fail = 1; break; }
             if (wall_clock64() - t0 > limit) {
                 xstore(err, 1u);
