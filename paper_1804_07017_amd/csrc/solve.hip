@@ -52,140 +52,258 @@ __device__ __forceinline__ void publish(T* x, int row, T y, bool valid, int* fla
     if (threadIdx.x == 0) xstore(flag, epoch);
 }
 
+// LU solves: a work-group solves two consecutive blocks (128 rows), so the
+// chain pays one publish / poll / fetch round trip per 128 rows instead of
+// per 64.  Wave 0 holds both blocks' rows (lane i: rows i and 64 + i) and runs
+// the 128-step substitution; all 8 waves accumulate the finished blocks.
+constexpr int kPR = 2 * kRB;               // rows per LU-solve work-group
+constexpr int kPThreads = 512;             // 4 column groups x 128 rows
+constexpr int kPG = kPThreads / kPR;
+constexpr int kPPerT = kPR / kPG;          // columns per thread per finished pair
+
 template <typename T>
-__global__ __launch_bounds__(kThreads) void trsv_lower_unit_kernel(const T* __restrict__ LU, long long lda, int n,
-                                                                    T* __restrict__ x, int* flags, int epoch,
-                                                                    unsigned* err, long long limit) {
-    __shared__ T part[4][kRB];
-    __shared__ T Ld[kRB][kRB + 1];
-    const int r = blockIdx.x;
-    const int tid = threadIdx.x, i = tid % kRB, g = tid / kRB;
-    const int row = r * kRB + i;
-    const int nb = min(kRB, n - r * kRB);
-    // this block's right-hand side, loaded before any wait (nothing else writes it)
-    const T b_row = (tid < kRB && row < n) ? x[row] : T(0);
-    // the diagonal block does not depend on other blocks: stage it first
-    for (int s = g; s < kRB; s += 4) Ld[s][i] = (row < n && s < nb) ? LU[row + (long long)(r * kRB + s) * lda] : T(0);
-    // this thread's slice of block (r, cb) of L: loaded one block ahead, before
-    // the wait for block cb's x, so that only x is fetched once the flag is up
-    constexpr int kPerT = kRB / 4;
-    auto load_l = [&](int cb, T (&lv)[kPerT]) {
-        const int j0 = cb * kRB;
+__device__ __forceinline__ T sum_parts(const T (&part)[kPG][kPR], int i) {
+    return (part[0][i] + part[1][i]) + (part[2][i] + part[3][i]);
+}
+
+// kRB serial substitution steps of a wave: at step sc, the chain value c of
+// lane sc (final by then) is broadcast and lanes on the unsolved side of sc
+// (below it, or above it when Up) subtract coef(sc) * c_sc; with Side, every
+// lane's second value (rows of the other block) subtracts side(sc) * c_sc.
+// coef(sc) = a[sc * lds + off_c + lane], side(sc) = a[sc * lds + off_s + lane],
+// in LDS.  The coefficients are fetched kCh steps ahead, and scheduling
+// barriers keep the compiler from moving the fetch of the next kCh steps
+// behind the current ones: each step then waits only for its multiply-add
+// and broadcast, never for an LDS round trip.
+template <typename T, bool Up, bool Side>
+__device__ __forceinline__ void chain_steps(const T* a, int lds, int off_c, int off_s, T& c, T& side) {
+    constexpr int kCh = 8, kNch = kRB / kCh;
+    const int lane = threadIdx.x;
+    T cc[kCh], cs[kCh];
+    auto fetch = [&](int ch, T (&vc)[kCh], T (&vs)[kCh]) {
 #pragma unroll
-        for (int u = 0; u < kPerT; ++u) lv[u] = (row < n) ? LU[row + (long long)(j0 + g + 4 * u) * lda] : T(0);
+        for (int k = 0; k < kCh; ++k) {
+            const int sc = Up ? kRB - 1 - (ch * kCh + k) : ch * kCh + k;
+            vc[k] = a[sc * lds + off_c + lane];
+            if constexpr (Side) vs[k] = a[sc * lds + off_s + lane];
+        }
     };
-    T acc = T(0);
-    T lv[kPerT];
-    if (r > 0) load_l(0, lv);
-    for (int cb = 0; cb < r; ++cb) {
-        T ln[kPerT];
-        if (cb + 1 < r) load_l(cb + 1, ln);
-        if (wait_flag(&flags[cb], epoch, err, limit)) return;
-        if (row < n) {
-            const int j0 = cb * kRB;
+    fetch(0, cc, cs);
 #pragma unroll
-            for (int u = 0; u < kPerT; ++u) acc += lv[u] * xload(&x[j0 + g + 4 * u]);
+    for (int ch = 0; ch < kNch; ++ch) {
+        T nc[kCh], ns[kCh];
+        if (ch + 1 < kNch) fetch(ch + 1, nc, ns);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < kCh; ++k) {
+            const int sc = Up ? kRB - 1 - (ch * kCh + k) : ch * kCh + k;
+            const T xs = lane_t(c, sc);                    // lane sc's value (sc is uniform)
+            c = (Up ? lane < sc : lane > sc) ? c - cc[k] * xs : c;
+            if constexpr (Side) side = side - cs[k] * xs;
         }
-        if (cb + 1 < r) {
+        __builtin_amdgcn_sched_barrier(0);
+        if (ch + 1 < kNch) {
 #pragma unroll
-            for (int u = 0; u < kPerT; ++u) lv[u] = ln[u];
+            for (int k = 0; k < kCh; ++k) {
+                cc[k] = nc[k];
+                if constexpr (Side) cs[k] = ns[k];
+            }
         }
     }
-    part[g][i] = acc;
+}
+
+// Wave 0 waits for pair p's flag (raised after both of its blocks' x values
+// completed) and copies those values (nvalid of them) into LDS; the other waves
+// meet it at the barrier.  Every wave of every waiting work-group used to load
+// the values itself: one copy per work-group cuts the requests to the few
+// cache lines that all of them want at the same moment.
+template <typename T>
+__device__ __forceinline__ bool wait_fetch_pair(const int* flag, int epoch, unsigned* err, long long limit,
+                                                const T* xp, int nvalid, T* xl) {
+    __shared__ int s_fail;
+    const int lane = threadIdx.x;
+    if (lane < kRB) {
+        int fail = 0;
+        const long long t0 = wall_clock64();
+        unsigned spins = 0;
+        // the flag, the error word and the clock are wave-uniform; as in
+        // wait_flag, the error word and the clock every 16th poll
+        while (xload(flag) != epoch) {
+            if ((++spins & 15u) != 0u) continue;
+            if (xload(err) != 0u) { fail = 1; break; }
+            if (wall_clock64() - t0 > limit) {
+                if (lane == 0) xstore(err, 1u);
+                fail = 1;
+                break;
+            }
+        }
+        if (!fail) {
+            xl[lane] = lane < nvalid ? xload(&xp[lane]) : T(0);
+            xl[kRB + lane] = kRB + lane < nvalid ? xload(&xp[kRB + lane]) : T(0);
+        }
+        if (lane == 0) s_fail = fail;
+    }
     __syncthreads();
-    T y = T(0);
+    return s_fail != 0;
+}
+
+// Publish both blocks of a pair: x values, then (after they completed) the
+// flags of block 2w and, if it exists, block 2w + 1.
+template <typename T>
+__device__ __forceinline__ void publish_pair(T* x, int n, int r0, T y0, T y1, int* flags, int w, int nblk,
+                                             int epoch) {
+    const int tid = threadIdx.x;
     if (tid < kRB) {
-        y = (row < n) ? b_row - ((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) : T(0);
-        // unrolled and branch-free, so that the LDS reads (independent of y)
-        // issue ahead of the serial chain instead of one round trip per step;
-        // columns past nb are zero and lanes past nb hold 0, so they change
-        // nothing
-#pragma unroll
-        for (int s = 0; s < kRB; ++s) {
-            const T l = Ld[s][i];
-            const T xs = lane_t(y, s);                 // lane s's value (s is uniform)
-            y = (i > s) ? y - l * xs : y;
-        }
+        if (r0 + tid < n) xstore(&x[r0 + tid], y0);
+        if (r0 + kRB + tid < n) xstore(&x[r0 + kRB + tid], y1);
     }
-    publish(x, row, y, tid < kRB && row < n, &flags[r], epoch);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) xstore(&flags[2 * w], epoch);
+    if (tid == 1 && 2 * w + 1 < nblk) xstore(&flags[2 * w + 1], epoch);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void trsv_upper_kernel(const T* __restrict__ LU, long long lda, int n,
-                                                               T* __restrict__ x, int* flags, int epoch,
-                                                               unsigned* err, long long limit) {
-    __shared__ T part[4][kRB];
-    __shared__ T Ud[kRB][kRB + 1];
+__global__ __launch_bounds__(kPThreads) void trsv_lower_unit_kernel(const T* __restrict__ LU, long long lda, int n,
+                                                                     T* __restrict__ x, int* flags, int epoch,
+                                                                     unsigned* err, long long limit) {
+    __shared__ T part[kPG][kPR];
+    __shared__ T La[kRB][kPR];     // La[s][i] = L(r0 + i, r0 + s): the first block's columns, all 128 rows
+    __shared__ T Lb[kRB][kRB];     // Lb[s][i] = L(r0 + 64 + i, r0 + 64 + s): the second block's diagonal
+    const int w = blockIdx.x;
     const int nblk = (n + kRB - 1) / kRB;
-    const int r = nblk - 1 - (int)blockIdx.x;         // bottom block first
-    const int tid = threadIdx.x, i = tid % kRB, g = tid / kRB;
-    const int row = r * kRB + i;
-    const int nb = min(kRB, n - r * kRB);
-    // this block's right-hand side, loaded before any wait (nothing else writes it)
-    const T b_row = (tid < kRB && row < n) ? x[row] : T(0);
-    for (int s = g; s < kRB; s += 4) Ud[s][i] = (row < n && s < nb) ? LU[row + (long long)(r * kRB + s) * lda] : T(0);
-    // block (r, cb) of U loaded one block ahead of the wait (as in the lower
-    // solve); columns past n (only in the last block) contribute zero
-    constexpr int kPerT = kRB / 4;
-    auto load_u = [&](int cb, T (&lv)[kPerT]) {
-        const int j0 = cb * kRB;
+    const int r0 = w * kPR;
+    const int tid = threadIdx.x, i = tid % kPR, g = tid / kPR;
+    const int row = r0 + i;
+    // both blocks' right-hand sides, loaded before any wait (nothing else writes them)
+    const T b0 = (tid < kRB && r0 + tid < n) ? x[r0 + tid] : T(0);
+    const T b1 = (tid < kRB && r0 + kRB + tid < n) ? x[r0 + kRB + tid] : T(0);
+    // the diagonal part does not depend on other blocks: stage it first
+    // (entries outside the matrix as zero)
+    for (int sc = g; sc < kRB; sc += kPG)
+        La[sc][i] = (row < n && r0 + sc < n) ? LU[row + (long long)(r0 + sc) * lda] : T(0);
+    for (int e = tid; e < kRB * kRB; e += kPThreads) {
+        const int sc = e / kRB, ii = e % kRB;
+        const int rr = r0 + kRB + ii, cc = r0 + kRB + sc;
+        Lb[sc][ii] = (rr < n && cc < n) ? LU[rr + (long long)cc * lda] : T(0);
+    }
+    // this thread's columns of the finished pair p (all inside the matrix,
+    // since p < w): loaded one pair ahead of the wait for p's x
+    auto load_l = [&](int p, T (&lv)[kPPerT]) {
+        const int j0 = p * kPR;
 #pragma unroll
-        for (int u = 0; u < kPerT; ++u) {
-            const int j = j0 + g + 4 * u;
-            lv[u] = (row < n && j < n) ? LU[row + (long long)j * lda] : T(0);
-        }
+        for (int u = 0; u < kPPerT; ++u) lv[u] = (row < n) ? LU[row + (long long)(j0 + g + kPG * u) * lda] : T(0);
     };
+    __shared__ T xl[2][kPR];       // the x values of a finished pair (double-buffered)
     T acc = T(0);
-    T lv[kPerT];
-    if (r < nblk - 1) load_u(nblk - 1, lv);
-    for (int cb = nblk - 1; cb > r; --cb) {
-        T ln[kPerT];
-        if (cb - 1 > r) load_u(cb - 1, ln);
-        if (wait_flag(&flags[cb], epoch, err, limit)) return;
+    T lv[kPPerT];
+    if (w > 0) load_l(0, lv);
+    for (int p = 0; p < w; ++p) {
+        T ln[kPPerT];
+        if (p + 1 < w) load_l(p + 1, ln);
+        T* xv = xl[p & 1];
+        if (wait_fetch_pair(&flags[2 * p], epoch, err, limit, x + p * kPR, kPR, xv)) return;
         if (row < n) {
-            const int j0 = cb * kRB;
-            const int nj = min(kRB, n - j0);
 #pragma unroll
-            for (int u = 0; u < kPerT; ++u)
-                if (g + 4 * u < nj) acc += lv[u] * xload(&x[j0 + g + 4 * u]);
+            for (int u = 0; u < kPPerT; ++u) acc += lv[u] * xv[g + kPG * u];
         }
-        if (cb - 1 > r) {
+        if (p + 1 < w) {
 #pragma unroll
-            for (int u = 0; u < kPerT; ++u) lv[u] = ln[u];
+            for (int u = 0; u < kPPerT; ++u) lv[u] = ln[u];
         }
     }
     part[g][i] = acc;
     __syncthreads();
-    T y = T(0);
+    T y0 = T(0), y1 = T(0);
     if (tid < kRB) {
-        y = (row < n) ? b_row - ((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) : T(0);
-        // branch-free, so that the LDS reads (independent of y) issue ahead of
-        // the serial chain instead of one round trip per step
-        if constexpr (sizeof(T) == 4) {
-            // FP32 (the working precision of the refinement's corrections): the
-            // diagonal's reciprocal is formed before the serial chain, which then
-            // multiplies (within 1.5 ulp of the division)
-            const T rd = (i < nb) ? T(1) / Ud[i][i] : T(0);
+        y0 = (r0 + tid < n) ? b0 - sum_parts(part, tid) : T(0);
+        y1 = (r0 + kRB + tid < n) ? b1 - sum_parts(part, kRB + tid) : T(0);
+        // rows and columns outside the matrix hold zero and change nothing
+        T none = T(0);
+        chain_steps<T, false, true>(&La[0][0], kPR, 0, kRB, y0, y1);    // the first block's columns
+        chain_steps<T, false, false>(&Lb[0][0], kRB, 0, 0, y1, none);   // the second block's diagonal
+    }
+    publish_pair(x, n, r0, y0, y1, flags, w, nblk, epoch);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kPThreads) void trsv_upper_kernel(const T* __restrict__ LU, long long lda, int n,
+                                                                T* __restrict__ x, int* flags, int epoch,
+                                                                unsigned* err, long long limit) {
+    // The pair's own part is solved as U' z = c with U' = U D^-1 (each column
+    // divided by its diagonal entry, so U' has a unit diagonal) and then
+    // x = D^-1 z: the divisions leave the serial chain, which is left with
+    // one multiply-add per step.  Scaled entries strictly above the diagonal:
+    __shared__ T part[kPG][kPR];
+    __shared__ T Uc[kRB][kPR];     // Uc[s][i] = U(r0 + i, r0 + 64 + s) / U(r0 + 64 + s, r0 + 64 + s), all 128 rows
+    __shared__ T Ut[kRB][kRB];     // Ut[s][i] = U(r0 + i, r0 + s) / U(r0 + s, r0 + s), the first block
+    __shared__ T dg[kPR];          // U(r0 + k, r0 + k)
+    const int nblk = (n + kRB - 1) / kRB;
+    const int npair = (nblk + 1) / 2;
+    const int w = npair - 1 - (int)blockIdx.x;       // bottom pair first
+    const int r0 = w * kPR;
+    const int tid = threadIdx.x, i = tid % kPR, g = tid / kPR;
+    const int row = r0 + i;
+    const T b0 = (tid < kRB && r0 + tid < n) ? x[r0 + tid] : T(0);
+    const T b1 = (tid < kRB && r0 + kRB + tid < n) ? x[r0 + kRB + tid] : T(0);
+    if (tid < kPR) dg[tid] = (r0 + tid < n) ? LU[(r0 + tid) + (long long)(r0 + tid) * lda] : T(0);
+    __syncthreads();
+    // entries on or below the diagonal and outside the matrix are zero (and
+    // never divided)
+    for (int sc = g; sc < kRB; sc += kPG) {
+        const int cc = r0 + kRB + sc;
+        Uc[sc][i] = (cc < n && i < kRB + sc) ? LU[row + (long long)cc * lda] / dg[kRB + sc] : T(0);
+    }
+    for (int e = tid; e < kRB * kRB; e += kPThreads) {
+        const int sc = e / kRB, ii = e % kRB;
+        const int cc = r0 + sc;
+        Ut[sc][ii] = (cc < n && ii < sc) ? LU[(r0 + ii) + (long long)cc * lda] / dg[sc] : T(0);
+    }
+    // pair p > w loaded one pair ahead of the wait; columns past n (only in
+    // the bottom pair) contribute zero
+    auto load_u = [&](int p, T (&lv)[kPPerT]) {
+        const int j0 = p * kPR;
 #pragma unroll
-            for (int s = kRB - 1; s >= 0; --s) {
-                const bool live = s < nb;                  // steps past a ragged block's end change nothing
-                const T u = Ud[s][i];
-                y = (live && i == s) ? y * rd : y;
-                const T xs = lane_t(y, s);             // lane s's value (s is uniform)
-                y = (live && i < s) ? y - u * xs : y;
-            }
-        } else {
+        for (int u = 0; u < kPPerT; ++u) {
+            const int j = j0 + g + kPG * u;
+            lv[u] = (row < n && j < n) ? LU[row + (long long)j * lda] : T(0);
+        }
+    };
+    __shared__ T xl[2][kPR];       // the x values of a finished pair (double-buffered)
+    T acc = T(0);
+    T lv[kPPerT];
+    if (w < npair - 1) load_u(npair - 1, lv);
+    for (int p = npair - 1; p > w; --p) {
+        T ln[kPPerT];
+        if (p - 1 > w) load_u(p - 1, ln);
+        T* xv = xl[p & 1];
+        // values past n (only in the bottom pair) read as zero, as do their U columns
+        if (wait_fetch_pair(&flags[2 * p], epoch, err, limit, x + p * kPR, min(kPR, n - p * kPR), xv)) return;
+        if (row < n) {
 #pragma unroll
-            for (int s = kRB - 1; s >= 0; --s) {
-                const bool live = s < nb;                  // steps past a ragged block's end change nothing
-                const T u = Ud[s][i];
-                y = (live && i == s) ? y / u : y;          // other lanes' quotients are dropped
-                const T xs = lane_t(y, s);             // lane s's value (s is uniform)
-                y = (live && i < s) ? y - u * xs : y;
-            }
+            for (int u = 0; u < kPPerT; ++u) acc += lv[u] * xv[g + kPG * u];
+        }
+        if (p - 1 > w) {
+#pragma unroll
+            for (int u = 0; u < kPPerT; ++u) lv[u] = ln[u];
         }
     }
-    publish(x, row, y, tid < kRB && row < n, &flags[r], epoch);
+    part[g][i] = acc;
+    __syncthreads();
+    T y0 = T(0), y1 = T(0);
+    if (tid < kRB) {
+        const bool in0 = r0 + tid < n, in1 = r0 + kRB + tid < n;
+        y0 = in0 ? b0 - sum_parts(part, tid) : T(0);
+        y1 = in1 ? b1 - sum_parts(part, kRB + tid) : T(0);
+        // unit upper substitution on the scaled entries, bottom up; a column
+        // outside the matrix has z = 0 and zero entries
+        T none = T(0);
+        chain_steps<T, true, true>(&Uc[0][0], kPR, kRB, 0, y1, y0);     // the second block's columns
+        chain_steps<T, true, false>(&Ut[0][0], kRB, 0, 0, y0, none);    // the first block's diagonal
+        y0 = in0 ? y0 / dg[tid] : T(0);
+        y1 = in1 ? y1 / dg[kRB + tid] : T(0);
+    }
+    publish_pair(x, n, r0, y0, y1, flags, w, nblk, epoch);
 }
 
 // Solves with a Cholesky factor (L lower, non-unit diagonal, A = L L^T).
@@ -369,6 +487,27 @@ __global__ __launch_bounds__(256) void gemv_partial_kernel(const double* __restr
     }
 }
 
+// The refinement's working copy and ||A||_inf in one pass over A:
+// dst = (float)A, partial[s][i] = sum over the columns of slice s of |A[i,j]|.
+__global__ __launch_bounds__(256) void convert_abs_partial_kernel(const double* __restrict__ A, long long lda, int n,
+                                                                  float* __restrict__ dst, long long ldd,
+                                                                  double* partial, int splits) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int s = blockIdx.y;
+    const int per = (n + splits - 1) / splits;
+    const int j0 = s * per, j1 = min(n, j0 + per);
+    double acc = 0.0;
+    if (i < n) {
+#pragma unroll 8
+        for (int j = j0; j < j1; ++j) {
+            const double a = A[i + (long long)j * lda];
+            dst[i + (long long)j * ldd] = (float)a;
+            acc += fabs(a);
+        }
+        partial[(long long)s * n + i] = acc;
+    }
+}
+
 __device__ __forceinline__ void atomic_max_abs(unsigned long long* out, double v) {
     // non-negative doubles order like their bit patterns; NaN bits sort above +inf
     atomicMax(out, (unsigned long long)__double_as_longlong(fabs(v)));
@@ -466,8 +605,8 @@ template <typename T>
 int launch_trsv_lower_unit(const T* LU, long long lda, int n, T* x, int* flags, int epoch, unsigned* err,
                            long long spin_limit, hipStream_t stream) {
     if (n <= 0) return 0;
-    const int nblk = (n + kRB - 1) / kRB;
-    hipLaunchKernelGGL((trsv_lower_unit_kernel<T>), dim3(nblk), dim3(kThreads), 0, stream, LU, lda, n, x, flags,
+    const int npair = ((n + kRB - 1) / kRB + 1) / 2;
+    hipLaunchKernelGGL((trsv_lower_unit_kernel<T>), dim3(npair), dim3(kPThreads), 0, stream, LU, lda, n, x, flags,
                        epoch, err, spin_limit);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -488,8 +627,8 @@ template <typename T>
 int launch_trsv_upper(const T* LU, long long lda, int n, T* x, int* flags, int epoch, unsigned* err,
                       long long spin_limit, hipStream_t stream) {
     if (n <= 0) return 0;
-    const int nblk = (n + kRB - 1) / kRB;
-    hipLaunchKernelGGL((trsv_upper_kernel<T>), dim3(nblk), dim3(kThreads), 0, stream, LU, lda, n, x, flags, epoch,
+    const int npair = ((n + kRB - 1) / kRB + 1) / 2;
+    hipLaunchKernelGGL((trsv_upper_kernel<T>), dim3(npair), dim3(kPThreads), 0, stream, LU, lda, n, x, flags, epoch,
                        err, spin_limit);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -509,6 +648,16 @@ int launch_row_abs_sums(const double* A, long long lda, int n, double* partial, 
     if (n <= 0) return 0;
     hipLaunchKernelGGL(gemv_partial_kernel, dim3((n + 255) / 256, splits), dim3(256), 0, stream, A, lda, n,
                        (const double*)nullptr, partial, splits);
+    hipLaunchKernelGGL(rowsum_max_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, partial, splits, n,
+                       reinterpret_cast<unsigned long long*>(out_max));
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_convert_row_abs_sums(const double* A, long long lda, int n, float* dst, long long ldd, double* partial,
+                                int splits, double* out_max, hipStream_t stream) {
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(convert_abs_partial_kernel, dim3((n + 255) / 256, splits), dim3(256), 0, stream, A, lda, n,
+                       dst, ldd, partial, splits);
     hipLaunchKernelGGL(rowsum_max_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, partial, splits, n,
                        reinterpret_cast<unsigned long long*>(out_max));
     return hipGetLastError() == hipSuccess ? 0 : -1;

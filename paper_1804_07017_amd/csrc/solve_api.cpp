@@ -17,6 +17,11 @@ namespace lu {
 
 int factor_impl(int n, void* A, int lda, lu_precision_t prec, int* ipiv, const lu_schedule_t* sched, int* d_info,
                 hipStream_t stream);
+// dst = (float)A (n x n, leading dimensions lda, ldd) and *out_max = ||A||_inf
+// as double bits (atomic max; clear it first), in one pass over A; partial
+// holds splits x n doubles.  Defined with the other solve kernels.
+int launch_convert_row_abs_sums(const double* A, long long lda, int n, float* dst, long long ldd, double* partial,
+                                int splits, double* out_max, hipStream_t stream);
 
 namespace {
 
@@ -160,11 +165,20 @@ int solve_ir_impl(int n, int nrhs, const double* A, int lda, const double* B, in
     if ((rc = ensure(s->ir_r, (size_t)n * sizeof(double)))) return rc;
     if ((rc = ensure(s->partial, (size_t)kSplits * n * sizeof(double)))) return rc;
     if ((rc = ensure(s->ir_norms, 16 * sizeof(double)))) return rc;
+    // the low-precision paths' FP32 working copy, made in the same pass over A
+    // as ||A||_inf
+    const bool low = prec != LU_FP64;
+    float* A32 = nullptr;
+    if (low) {
+        if ((rc = ensure(s->ir_a32, (size_t)n * n * sizeof(float)))) return rc;
+        A32 = reinterpret_cast<float*>(s->ir_a32.ptr);
+    }
     // ||A||_inf and a finiteness check of the inputs
     unsigned long long* nrm = reinterpret_cast<unsigned long long*>(s->ir_norms.ptr);
     if (launch_fill_zero(nrm, sizeof(unsigned long long), stream)) return LU_ERR_HIP;
-    if (launch_row_abs_sums(A, lda, n, reinterpret_cast<double*>(s->partial.ptr), kSplits,
-                            reinterpret_cast<double*>(nrm), stream))
+    double* part = reinterpret_cast<double*>(s->partial.ptr);
+    if (low ? launch_convert_row_abs_sums(A, lda, n, A32, n, part, kSplits, reinterpret_cast<double*>(nrm), stream)
+            : launch_row_abs_sums(A, lda, n, part, kSplits, reinterpret_cast<double*>(nrm), stream))
         return LU_ERR_HIP;
     unsigned long long abits = 0;
     LU_HIP(hipMemcpyAsync(&abits, nrm, sizeof abits, hipMemcpyDeviceToHost, stream));
@@ -200,14 +214,11 @@ int solve_ir_impl(int n, int nrhs, const double* A, int lda, const double* B, in
     };
     if (prec == LU_FP64) return fp64_solution(false);
 
-    // low-precision factorization of an FP32 working copy
-    if ((rc = ensure(s->ir_a32, (size_t)n * n * sizeof(float)))) return rc;
+    // low-precision factorization of the FP32 working copy
     if ((rc = ensure(s->ir_ipiv, (size_t)n * sizeof(int)))) return rc;
     if ((rc = ensure(s->ir_x32, (size_t)n * sizeof(float)))) return rc;
-    float* A32 = reinterpret_cast<float*>(s->ir_a32.ptr);
     int* ipiv = reinterpret_cast<int*>(s->ir_ipiv.ptr);
     float* d32 = reinterpret_cast<float*>(s->ir_x32.ptr);
-    if (launch_convert_f64_f32(A, lda, A32, n, n, n, stream)) return LU_ERR_HIP;
     if ((rc = factor_impl(n, A32, n, prec, ipiv, nullptr, nullptr, stream))) return rc;
     int info_lp = 0;
     if ((rc = factor_status(s, stream, &info_lp))) return rc;
