@@ -54,16 +54,54 @@ __device__ __forceinline__ void publish(T* x, int row, T y, bool valid, int* fla
 
 // LU solves: a work-group solves two consecutive blocks (128 rows), so the
 // chain pays one publish / poll / fetch round trip per 128 rows instead of
-// per 64.  Wave 0 holds both blocks' rows (lane i: rows i and 64 + i) and runs
-// the 128-step substitution; all 8 waves accumulate the finished blocks.
+// per 64.  Wave 0 polls, copies finished x values into LDS, holds both blocks'
+// rows (lane i: rows i and 64 + i) for the 128-step substitution and
+// publishes; 512 threads (4 column groups x 128 rows) prefetch the finished
+// pairs' coefficients and accumulate.  A wave's loads complete in issue order,
+// so a poll issued behind a prefetch waits for it: in FP32 wave 0 is a control
+// wave of its own, with no prefetch.  In FP64 wave 0 also accumulates: a
+// ninth wave would cap the registers at 168 per lane, and the FP64 kernel then
+// spills (measured slower than the wait behind its own prefetch).
 constexpr int kPR = 2 * kRB;               // rows per LU-solve work-group
-constexpr int kPThreads = 512;             // 4 column groups x 128 rows
-constexpr int kPG = kPThreads / kPR;
-constexpr int kPPerT = kPR / kPG;          // columns per thread per finished pair
-
 template <typename T>
-__device__ __forceinline__ T sum_parts(const T (&part)[kPG][kPR], int i) {
-    return (part[0][i] + part[1][i]) + (part[2][i] + part[3][i]);
+struct Pair {
+    static constexpr bool own_ctl = sizeof(T) == 4;   // a control wave of its own
+    static constexpr int acc = 512;                   // accumulating threads
+    static constexpr int first = own_ctl ? kRB : 0;   // the first of them
+    static constexpr int threads = first + acc;
+    static constexpr int groups = acc / kPR;
+    static constexpr int per = kPR / groups;          // columns per thread per finished pair
+};
+
+// Column loads of one wave: the matrix from a pair's first column on as a
+// buffer resource (scalar registers).  Element (r, c0 + dc) is at byte offset
+// r * sizeof(T), the one vector operand, plus dc * lda * sizeof(T), a scalar
+// offset when dc is uniform in the wave.  (Generic 64-bit addresses per load
+// would cost two vector registers each, which the compiler keeps live across
+// the wait loop.)  Offsets stay below 2^31 while 128 * lda * sizeof(T) does.
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t cols_rsrc(const T* c0) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(c0), (short)0, 0x7fffffff, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T ld_rsrc(__amdgpu_buffer_rsrc_t rs, int voff, int soff) {
+    if constexpr (sizeof(T) == 8) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+    else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
+}
+
+// a(r, c) with the row and column clamped into the n x n matrix: every lane
+// loads from a valid address, so no branch is wrapped around the load (a
+// conditional load is compiled as a branch, and the loads of a prefetch then
+// stop overlapping); callers discard or zero what lies outside
+template <typename T>
+__device__ __forceinline__ T ld_in(const T* a, long long lda, int r, int c, int n) {
+    return a[min(r, n - 1) + (long long)min(c, n - 1) * lda];
+}
+
+template <typename T, int G>
+__device__ __forceinline__ T sum_parts(const T (&part)[G][kPR], int i) {
+    if constexpr (G == 2) return part[0][i] + part[1][i];
+    else return (part[0][i] + part[1][i]) + (part[2][i] + part[3][i]);
 }
 
 // kRB serial substitution steps of a wave: at step sc, the chain value c of
@@ -164,55 +202,65 @@ __device__ __forceinline__ void publish_pair(T* x, int n, int r0, T y0, T y1, in
 }
 
 template <typename T>
-__global__ __launch_bounds__(kPThreads) void trsv_lower_unit_kernel(const T* __restrict__ LU, long long lda, int n,
+__global__ __launch_bounds__(Pair<T>::threads) void trsv_lower_unit_kernel(const T* __restrict__ LU, long long lda, int n,
                                                                      T* __restrict__ x, int* flags, int epoch,
                                                                      unsigned* err, long long limit) {
+    constexpr int kPThreads = Pair<T>::threads, kPG = Pair<T>::groups, kPPerT = Pair<T>::per;
     __shared__ T part[kPG][kPR];
     __shared__ T La[kRB][kPR];     // La[s][i] = L(r0 + i, r0 + s): the first block's columns, all 128 rows
     __shared__ T Lb[kRB][kRB];     // Lb[s][i] = L(r0 + 64 + i, r0 + 64 + s): the second block's diagonal
     const int w = blockIdx.x;
     const int nblk = (n + kRB - 1) / kRB;
     const int r0 = w * kPR;
-    const int tid = threadIdx.x, i = tid % kPR, g = tid / kPR;
+    const int tid = threadIdx.x;
+    const bool acc_t = tid >= Pair<T>::first;         // an accumulating thread: row i, column group g
+    const int at = acc_t ? tid - Pair<T>::first : 0;
+    const int i = at % kPR, g = at / kPR;
     const int row = r0 + i;
     // both blocks' right-hand sides, loaded before any wait (nothing else writes them)
-    const T b0 = (tid < kRB && r0 + tid < n) ? x[r0 + tid] : T(0);
-    const T b1 = (tid < kRB && r0 + kRB + tid < n) ? x[r0 + kRB + tid] : T(0);
+    const T b0 = x[min(r0 + tid % kRB, n - 1)];     // used only by wave 0, for rows inside the matrix
+    const T b1 = x[min(r0 + kRB + tid % kRB, n - 1)];
     // the diagonal part does not depend on other blocks: stage it first
     // (entries outside the matrix as zero)
-    for (int sc = g; sc < kRB; sc += kPG)
-        La[sc][i] = (row < n && r0 + sc < n) ? LU[row + (long long)(r0 + sc) * lda] : T(0);
+    if (acc_t) {
+        for (int sc = g; sc < kRB; sc += kPG) {
+            const T v = ld_in(LU, lda, row, r0 + sc, n);
+            La[sc][i] = (row < n && r0 + sc < n) ? v : T(0);
+        }
+    }
     for (int e = tid; e < kRB * kRB; e += kPThreads) {
         const int sc = e / kRB, ii = e % kRB;
         const int rr = r0 + kRB + ii, cc = r0 + kRB + sc;
-        Lb[sc][ii] = (rr < n && cc < n) ? LU[rr + (long long)cc * lda] : T(0);
+        const T v = ld_in(LU, lda, rr, cc, n);
+        Lb[sc][ii] = (rr < n && cc < n) ? v : T(0);
     }
-    // this thread's columns of the finished pair p (all inside the matrix,
-    // since p < w): loaded one pair ahead of the wait for p's x
+    // this thread's columns of the finished pair p (inside the matrix, since
+    // p < w; rows past n load row n - 1 and their sums are discarded).  The
+    // next pair's are loaded right after this pair's are used, so they are
+    // in flight during the next wait.
+    // (g is uniform in a wave, so the column offsets are scalar)
+    const int gu = __builtin_amdgcn_readfirstlane(g);
+    const int voff = min(row, n - 1) * (int)sizeof(T);
+    const int ldb = (int)lda * (int)sizeof(T);
     auto load_l = [&](int p, T (&lv)[kPPerT]) {
-        const int j0 = p * kPR;
+        const auto rs = cols_rsrc(LU + (long long)p * kPR * lda);
 #pragma unroll
-        for (int u = 0; u < kPPerT; ++u) lv[u] = (row < n) ? LU[row + (long long)(j0 + g + kPG * u) * lda] : T(0);
+        for (int u = 0; u < kPPerT; ++u) lv[u] = ld_rsrc<T>(rs, voff, (gu + kPG * u) * ldb);
     };
     __shared__ T xl[2][kPR];       // the x values of a finished pair (double-buffered)
     T acc = T(0);
     T lv[kPPerT];
-    if (w > 0) load_l(0, lv);
+    if (w > 0 && acc_t) load_l(0, lv);
     for (int p = 0; p < w; ++p) {
-        T ln[kPPerT];
-        if (p + 1 < w) load_l(p + 1, ln);
         T* xv = xl[p & 1];
         if (wait_fetch_pair(&flags[2 * p], epoch, err, limit, x + p * kPR, kPR, xv)) return;
-        if (row < n) {
+        if (acc_t) {
 #pragma unroll
             for (int u = 0; u < kPPerT; ++u) acc += lv[u] * xv[g + kPG * u];
-        }
-        if (p + 1 < w) {
-#pragma unroll
-            for (int u = 0; u < kPPerT; ++u) lv[u] = ln[u];
+            if (p + 1 < w) load_l(p + 1, lv);
         }
     }
-    part[g][i] = acc;
+    if (acc_t) part[g][i] = acc;
     __syncthreads();
     T y0 = T(0), y1 = T(0);
     if (tid < kRB) {
@@ -227,9 +275,10 @@ __global__ __launch_bounds__(kPThreads) void trsv_lower_unit_kernel(const T* __r
 }
 
 template <typename T>
-__global__ __launch_bounds__(kPThreads) void trsv_upper_kernel(const T* __restrict__ LU, long long lda, int n,
+__global__ __launch_bounds__(Pair<T>::threads) void trsv_upper_kernel(const T* __restrict__ LU, long long lda, int n,
                                                                 T* __restrict__ x, int* flags, int epoch,
                                                                 unsigned* err, long long limit) {
+    constexpr int kPThreads = Pair<T>::threads, kPG = Pair<T>::groups, kPPerT = Pair<T>::per;
     // The pair's own part is solved as U' z = c with U' = U D^-1 (each column
     // divided by its diagonal entry, so U' has a unit diagonal) and then
     // x = D^-1 z: the divisions leave the serial chain, which is left with
@@ -242,53 +291,63 @@ __global__ __launch_bounds__(kPThreads) void trsv_upper_kernel(const T* __restri
     const int npair = (nblk + 1) / 2;
     const int w = npair - 1 - (int)blockIdx.x;       // bottom pair first
     const int r0 = w * kPR;
-    const int tid = threadIdx.x, i = tid % kPR, g = tid / kPR;
+    const int tid = threadIdx.x;
+    const bool acc_t = tid >= Pair<T>::first;         // an accumulating thread: row i, column group g
+    const int at = acc_t ? tid - Pair<T>::first : 0;
+    const int i = at % kPR, g = at / kPR;
     const int row = r0 + i;
-    const T b0 = (tid < kRB && r0 + tid < n) ? x[r0 + tid] : T(0);
-    const T b1 = (tid < kRB && r0 + kRB + tid < n) ? x[r0 + kRB + tid] : T(0);
-    if (tid < kPR) dg[tid] = (r0 + tid < n) ? LU[(r0 + tid) + (long long)(r0 + tid) * lda] : T(0);
+    const T b0 = x[min(r0 + tid % kRB, n - 1)];     // used only by wave 0, for rows inside the matrix
+    const T b1 = x[min(r0 + kRB + tid % kRB, n - 1)];
+    if (tid < kPR) {
+        const T v = ld_in(LU, lda, r0 + tid, r0 + tid, n);
+        dg[tid] = (r0 + tid < n) ? v : T(0);
+    }
     __syncthreads();
-    // entries on or below the diagonal and outside the matrix are zero (and
-    // never divided)
-    for (int sc = g; sc < kRB; sc += kPG) {
-        const int cc = r0 + kRB + sc;
-        Uc[sc][i] = (cc < n && i < kRB + sc) ? LU[row + (long long)cc * lda] / dg[kRB + sc] : T(0);
+    // entries on or below the diagonal and outside the matrix are zero (the
+    // quotients of those are discarded)
+    if (acc_t) {
+        for (int sc = g; sc < kRB; sc += kPG) {
+            const int cc = r0 + kRB + sc;
+            const T v = ld_in(LU, lda, row, cc, n) / dg[kRB + sc];
+            Uc[sc][i] = (cc < n && i < kRB + sc) ? v : T(0);
+        }
     }
     for (int e = tid; e < kRB * kRB; e += kPThreads) {
         const int sc = e / kRB, ii = e % kRB;
         const int cc = r0 + sc;
-        Ut[sc][ii] = (cc < n && ii < sc) ? LU[(r0 + ii) + (long long)cc * lda] / dg[sc] : T(0);
+        const T v = ld_in(LU, lda, r0 + ii, cc, n) / dg[sc];
+        Ut[sc][ii] = (cc < n && ii < sc) ? v : T(0);
     }
-    // pair p > w loaded one pair ahead of the wait; columns past n (only in
-    // the bottom pair) contribute zero
+    // pair p > w, loaded right after pair p + 1 is used (as in the lower
+    // solve); rows past n are discarded, and columns past n (only in the
+    // bottom pair) are zeroed when used, with their x
+    // (scalar column offsets, as in the lower solve)
+    const int gu = __builtin_amdgcn_readfirstlane(g);
+    const int voff = min(row, n - 1) * (int)sizeof(T);
+    const int ldb = (int)lda * (int)sizeof(T);
     auto load_u = [&](int p, T (&lv)[kPPerT]) {
-        const int j0 = p * kPR;
+        const auto rs = cols_rsrc(LU + (long long)p * kPR * lda);
 #pragma unroll
-        for (int u = 0; u < kPPerT; ++u) {
-            const int j = j0 + g + kPG * u;
-            lv[u] = (row < n && j < n) ? LU[row + (long long)j * lda] : T(0);
-        }
+        for (int u = 0; u < kPPerT; ++u) lv[u] = ld_rsrc<T>(rs, voff, (min(p * kPR + gu + kPG * u, n - 1) - p * kPR) * ldb);
     };
     __shared__ T xl[2][kPR];       // the x values of a finished pair (double-buffered)
     T acc = T(0);
     T lv[kPPerT];
-    if (w < npair - 1) load_u(npair - 1, lv);
+    if (w < npair - 1 && acc_t) load_u(npair - 1, lv);
     for (int p = npair - 1; p > w; --p) {
-        T ln[kPPerT];
-        if (p - 1 > w) load_u(p - 1, ln);
         T* xv = xl[p & 1];
-        // values past n (only in the bottom pair) read as zero, as do their U columns
+        // values past n read as zero
         if (wait_fetch_pair(&flags[2 * p], epoch, err, limit, x + p * kPR, min(kPR, n - p * kPR), xv)) return;
-        if (row < n) {
+        if (acc_t) {
 #pragma unroll
-            for (int u = 0; u < kPPerT; ++u) acc += lv[u] * xv[g + kPG * u];
-        }
-        if (p - 1 > w) {
-#pragma unroll
-            for (int u = 0; u < kPPerT; ++u) lv[u] = ln[u];
+            for (int u = 0; u < kPPerT; ++u) {
+                const T l = p * kPR + g + kPG * u < n ? lv[u] : T(0);
+                acc += l * xv[g + kPG * u];
+            }
+            if (p - 1 > w) load_u(p - 1, lv);
         }
     }
-    part[g][i] = acc;
+    if (acc_t) part[g][i] = acc;
     __syncthreads();
     T y0 = T(0), y1 = T(0);
     if (tid < kRB) {
@@ -606,7 +665,7 @@ int launch_trsv_lower_unit(const T* LU, long long lda, int n, T* x, int* flags, 
                            long long spin_limit, hipStream_t stream) {
     if (n <= 0) return 0;
     const int npair = ((n + kRB - 1) / kRB + 1) / 2;
-    hipLaunchKernelGGL((trsv_lower_unit_kernel<T>), dim3(npair), dim3(kPThreads), 0, stream, LU, lda, n, x, flags,
+    hipLaunchKernelGGL((trsv_lower_unit_kernel<T>), dim3(npair), dim3(Pair<T>::threads), 0, stream, LU, lda, n, x, flags,
                        epoch, err, spin_limit);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -628,7 +687,7 @@ int launch_trsv_upper(const T* LU, long long lda, int n, T* x, int* flags, int e
                       long long spin_limit, hipStream_t stream) {
     if (n <= 0) return 0;
     const int npair = ((n + kRB - 1) / kRB + 1) / 2;
-    hipLaunchKernelGGL((trsv_upper_kernel<T>), dim3(npair), dim3(kPThreads), 0, stream, LU, lda, n, x, flags, epoch,
+    hipLaunchKernelGGL((trsv_upper_kernel<T>), dim3(npair), dim3(Pair<T>::threads), 0, stream, LU, lda, n, x, flags, epoch,
                        err, spin_limit);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
