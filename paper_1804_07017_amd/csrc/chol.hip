@@ -60,7 +60,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_panel_kernel(CholPanelArgs<
     if (g == 0 && tid == 0 && a.sync_next) xstore_s<S>(a.sync_next, 0u);
     const int stride = kCholThreads * P;
     constexpr int kChunk = kChunkCols;                      // columns per pass of the in-panel update
-    constexpr bool kPrefetch = kCholRows <= 2;              // registers for a second chunk
+    constexpr int kDepth = kCholRows <= 2 ? 4 : 1;          // chunks in flight (as registers allow)
 
     for (int cb = 0; cb < w; cb += kCholNB) {
         const int nbw = min(kCholNB, w - cb);
@@ -143,56 +143,72 @@ __global__ __launch_bounds__(kCholThreads) void chol_panel_kernel(CholPanelArgs<
         }
         if (right0 >= w) break;
         // 3. the panel columns right of the block, lower triangle, kChunk
-        //    columns at a time (every row's loads of a chunk in flight together)
+        //    columns at a time.  Every load is unconditional (clamped
+        //    address): a conditional load compiles to a branch, and each one
+        //    then waits for its round trip before the next is issued.
         {
             const int wr = (w - right0 + kChunk - 1) / kChunk * kChunk;     // zero past w: whole chunks
-            for (int e = tid; e < wr * kCholNB; e += kCholThreads) {
-                const int c = e % wr, k = e / wr;
-                UtT[k][c] = (k < nbw && right0 + c < w) ? cload<S>(A + (right0 + c) + (long long)(cb + k) * lda) : T(0);
+            const int ne = wr * kCholNB;
+            constexpr int kBatch = 16;                                      // loads in flight per thread
+            for (int e0 = 0; e0 < ne; e0 += kBatch * kCholThreads) {
+                T t[kBatch];
+#pragma unroll
+                for (int q = 0; q < kBatch; ++q) {
+                    const int e = min(e0 + q * kCholThreads + tid, ne - 1);
+                    const int c = e % wr, k = e / wr;
+                    t[q] = cload<S>(A + min(right0 + c, w - 1) + (long long)(cb + min(k, nbw - 1)) * lda);
+                }
+#pragma unroll
+                for (int q = 0; q < kBatch; ++q) {
+                    const int e = e0 + q * kCholThreads + tid;
+                    const int c = e % wr, k = e / wr;
+                    if (e < ne) UtT[k][c] = (k < nbw && right0 + c < w) ? t[q] : T(0);
+                }
             }
         }
         __syncthreads();
+        // Chunks of this thread's rows, kDepth of them in flight: a chunk is
+        // loaded kDepth chunks ahead of its arithmetic.  Elements outside the
+        // lower triangle or the panel are loaded from a clamped address,
+        // updated and never stored.
         auto load_chunk = [&](int c0, T (&v)[kCholRows][kChunk]) {
 #pragma unroll
             for (int r = 0; r < kCholRows; ++r) {
-                const int i = row0 + r * stride;
+                const int ic = min(row0 + r * stride, m - 1);
 #pragma unroll
-                for (int cc = 0; cc < kChunk; ++cc) {
-                    const int c = c0 + cc;
-                    v[r][cc] = (i < m && c < w && c <= i) ? cload<S>(A + i + (long long)c * lda) : T(0);
-                }
+                for (int cc = 0; cc < kChunk; ++cc) v[r][cc] = cload<S>(A + ic + (long long)min(c0 + cc, w - 1) * lda);
             }
         };
-        // the next chunk's loads are issued before this chunk's arithmetic
-        T v[kCholRows][kChunk];
-        load_chunk(right0, v);
-        for (int c0 = right0; c0 < w; c0 += kChunk) {
-            T vn[kCholRows][kChunk];
-            if (kPrefetch && c0 + kChunk < w) load_chunk(c0 + kChunk, vn);
+        const int nch = (w - right0 + kChunk - 1) / kChunk;
+        T v[kDepth][kCholRows][kChunk];
 #pragma unroll
-            for (int cc = 0; cc < kChunk; ++cc) {
+        for (int d = 0; d < kDepth; ++d)
+            if (d < nch) load_chunk(right0 + d * kChunk, v[d]);
+        for (int ch = 0; ch < nch; ch += kDepth) {
 #pragma unroll
-                for (int k = 0; k < kCholNB; ++k) {
-                    const T u = UtT[k][c0 - right0 + cc];
-#pragma unroll
-                    for (int r = 0; r < kCholRows; ++r) v[r][cc] = v[r][cc] - x[r][k] * u;
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < kCholRows; ++r) {
-                const int i = row0 + r * stride;
+            for (int d = 0; d < kDepth; ++d) {
+                const int q = ch + d;
+                if (q >= nch) break;
+                const int c0 = right0 + q * kChunk;
 #pragma unroll
                 for (int cc = 0; cc < kChunk; ++cc) {
-                    const int c = c0 + cc;
-                    if (i < m && c < w && c <= i) cstore<S>(A + i + (long long)c * lda, v[r][cc]);
+#pragma unroll
+                    for (int k = 0; k < kCholNB; ++k) {
+                        const T u = UtT[k][c0 - right0 + cc];
+#pragma unroll
+                        for (int r = 0; r < kCholRows; ++r) v[d][r][cc] = v[d][r][cc] - x[r][k] * u;
+                    }
                 }
-            }
-            if (c0 + kChunk < w) {
-                if (!kPrefetch) load_chunk(c0 + kChunk, vn);
 #pragma unroll
-                for (int r = 0; r < kCholRows; ++r)
+                for (int r = 0; r < kCholRows; ++r) {
+                    const int i = row0 + r * stride;
 #pragma unroll
-                    for (int cc = 0; cc < kChunk; ++cc) v[r][cc] = vn[r][cc];
+                    for (int cc = 0; cc < kChunk; ++cc) {
+                        const int c = c0 + cc;
+                        if (i < m && c < w && c <= i) cstore<S>(A + i + (long long)c * lda, v[d][r][cc]);
+                    }
+                }
+                if (q + kDepth < nch) load_chunk(c0 + kDepth * kChunk, v[d]);
             }
         }
         if (grid_barrier_nofence(a.sync, a.sync + 1, ++epoch, a.spin_limit, P)) return;
