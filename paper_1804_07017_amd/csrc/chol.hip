@@ -59,8 +59,8 @@ __global__ __launch_bounds__(kCholThreads) void chol_panel_kernel(CholPanelArgs<
     // the next launch's barrier counter (its previous user has finished)
     if (g == 0 && tid == 0 && a.sync_next) xstore_s<S>(a.sync_next, 0u);
     const int stride = kCholThreads * P;
-    constexpr int kChunk = kChunkCols;                      // columns per pass of the in-panel update
-    constexpr int kDepth = kCholRows <= 2 ? 4 : 1;          // chunks in flight (as registers allow)
+    constexpr int kChunk = kCholRows <= 2 ? kChunkCols : kChunkCols / 2;   // columns per pass of the in-panel update
+    constexpr int kDepth = kCholRows <= 2 ? 4 : 2;          // chunks in flight (as registers allow)
 
     for (int cb = 0; cb < w; cb += kCholNB) {
         const int nbw = min(kCholNB, w - cb);

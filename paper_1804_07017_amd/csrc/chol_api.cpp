@@ -58,10 +58,13 @@ int chol_execute(DeviceState* s, int n, double* A, long long lda, int* info, int
             pa.sync_next = s->sync + 2 * (1 - s->sync_slot);
             s->sync_slot = 1 - s->sync_slot;
             pa.spin_limit = s->spin_limit;
-            // one group per 512 panel rows (two per thread), at least the panel
-            // CU share, at most 64 and the CU count (every group must be
-            // resident at once); past 64 x 512 rows, four rows per thread
-            int wgs = std::max((pa.m + 511) / 512, std::max(1, panel_cus));
+            // one group per 1024 panel rows (four per thread; two once the
+            // panel CU share gives enough groups), at least the panel CU share,
+            // at most 64 and the CU count (every group must be resident at
+            // once).  Fewer groups leave more CUs to the symmetric update
+            // running beside the panel: at n = 32768, 32 groups of four rows
+            // per thread take 303 ms against 322 ms for 64 groups of two.
+            int wgs = std::max((pa.m + 1023) / 1024, std::max(1, panel_cus));
             wgs = std::min(wgs, std::min(64, s->num_cus));
             wgs = std::min(wgs, std::max(1, (pa.m + 255) / 256));
             if ((long long)wgs * 1024 < pa.m) return LU_ERR_UNSUPPORTED;   // > 4 rows per thread
