@@ -163,7 +163,11 @@ def test_planted_factors_recovered(gpu, n):
     assert np.abs(Uh - U).max() <= 1e-12 * np.abs(U).max()
 
 
-@pytest.mark.parametrize("n,nrhs", [(512, 1), (2000, 3), (100, 1)])
+# the triangular solves take 64-row blocks two per work-group: an odd number of
+# blocks (37, 130, 191, 4160) leaves a work-group with one block, and ragged
+# sizes a partial block
+@pytest.mark.parametrize("n,nrhs", [(512, 1), (2000, 3), (100, 1), (1, 1), (37, 2), (64, 1), (130, 2), (191, 1),
+                                    (4160, 1)])
 def test_solve_matches_oracle(gpu, n, nrhs):
     import torch
     A = synth.uniform(n, seed=n)
