@@ -73,12 +73,13 @@ struct Pair {
     static constexpr int per = kPR / groups;          // columns per thread per finished pair
 };
 
-// Column loads of one wave: the matrix from a pair's first column on as a
-// buffer resource (scalar registers).  Element (r, c0 + dc) is at byte offset
-// r * sizeof(T), the one vector operand, plus dc * lda * sizeof(T), a scalar
-// offset when dc is uniform in the wave.  (Generic 64-bit addresses per load
+// Column loads of one wave: a column, uniform in the wave, as a buffer
+// resource (scalar registers); element r of it is at byte offset
+// r * sizeof(T), the one vector operand.  (Generic 64-bit addresses per load
 // would cost two vector registers each, which the compiler keeps live across
-// the wait loop.)  Offsets stay below 2^31 while 128 * lda * sizeof(T) does.
+// the wait loop.)  Resource: stride 0 (raw offsets), 2^31 - 1 bytes of range,
+// and word 3 = 0x00020000, the 32-bit data format that gfx9 untyped buffer
+// loads need (a zero format reads as zero).
 template <typename T>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t cols_rsrc(const T* c0) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(c0), (short)0, 0x7fffffff, 0x00020000);
@@ -238,14 +239,13 @@ __global__ __launch_bounds__(Pair<T>::threads) void trsv_lower_unit_kernel(const
     // p < w; rows past n load row n - 1 and their sums are discarded).  The
     // next pair's are loaded right after this pair's are used, so they are
     // in flight during the next wait.
-    // (g is uniform in a wave, so the column offsets are scalar)
+    // (g is uniform in a wave, so each column address is scalar)
     const int gu = __builtin_amdgcn_readfirstlane(g);
     const int voff = min(row, n - 1) * (int)sizeof(T);
-    const int ldb = (int)lda * (int)sizeof(T);
     auto load_l = [&](int p, T (&lv)[kPPerT]) {
-        const auto rs = cols_rsrc(LU + (long long)p * kPR * lda);
 #pragma unroll
-        for (int u = 0; u < kPPerT; ++u) lv[u] = ld_rsrc<T>(rs, voff, (gu + kPG * u) * ldb);
+        for (int u = 0; u < kPPerT; ++u)
+            lv[u] = ld_rsrc<T>(cols_rsrc(LU + (long long)(p * kPR + gu + kPG * u) * lda), voff, 0);
     };
     __shared__ T xl[2][kPR];       // the x values of a finished pair (double-buffered)
     T acc = T(0);
@@ -321,14 +321,13 @@ __global__ __launch_bounds__(Pair<T>::threads) void trsv_upper_kernel(const T* _
     // pair p > w, loaded right after pair p + 1 is used (as in the lower
     // solve); rows past n are discarded, and columns past n (only in the
     // bottom pair) are zeroed when used, with their x
-    // (scalar column offsets, as in the lower solve)
+    // (scalar column addresses, as in the lower solve)
     const int gu = __builtin_amdgcn_readfirstlane(g);
     const int voff = min(row, n - 1) * (int)sizeof(T);
-    const int ldb = (int)lda * (int)sizeof(T);
     auto load_u = [&](int p, T (&lv)[kPPerT]) {
-        const auto rs = cols_rsrc(LU + (long long)p * kPR * lda);
 #pragma unroll
-        for (int u = 0; u < kPPerT; ++u) lv[u] = ld_rsrc<T>(rs, voff, (min(p * kPR + gu + kPG * u, n - 1) - p * kPR) * ldb);
+        for (int u = 0; u < kPPerT; ++u)
+            lv[u] = ld_rsrc<T>(cols_rsrc(LU + (long long)min(p * kPR + gu + kPG * u, n - 1) * lda), voff, 0);
     };
     __shared__ T xl[2][kPR];       // the x values of a finished pair (double-buffered)
     T acc = T(0);

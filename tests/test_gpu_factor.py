@@ -186,6 +186,27 @@ def test_solve_matches_oracle(gpu, n, nrhs):
     assert np.abs(X - Xo).max() <= 1e-8 * np.abs(Xo).max()
 
 
+def test_solve_leading_dimension_past_2gib(gpu):
+    """Columns more than 2^31 bytes apart (lda * 8 * 300 > 2^31): the solve's
+    column addresses are formed per column, not as 32-bit offsets from one base."""
+    import torch
+    n, lda = 300, (1 << 21) + 64
+    A = synth.uniform(n, seed=11)
+    B = synth.rhs(n, seed=11, nrhs=1)
+    LU, ipiv, _ = _factor(gpu, A, 128, 1)
+    dLU = gpu.to_device(LU, lda=lda)
+    dp = torch.tensor(ipiv, dtype=torch.int32, device="cuda")
+    dB = gpu.to_device(B)
+    assert gpu.lu_solve_ex(dLU, dp, dB) == 0
+    torch.cuda.synchronize()
+    X = gpu.to_host(dB)
+    oLU, oip, _ = oracle.getrf(A, nthreads=8)
+    Xo = oracle.getrs(oLU, oip, B)
+    assert np.abs(X - Xo).max() <= 1e-8 * np.abs(Xo).max()
+    del dLU
+    torch.cuda.empty_cache()
+
+
 def test_solve_square_default_stream_form(gpu):
     import torch
     n = 333
