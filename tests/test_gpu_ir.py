@@ -36,7 +36,7 @@ def _forward_error_bound(A, n):
 
 
 @pytest.mark.parametrize("prec", [2, 3])          # LU_MIXED_FP16, LU_MIXED_BF16
-@pytest.mark.parametrize("n", [2048, 1000])
+@pytest.mark.parametrize("n", [2048, 1000, 777])  # 777: 13 blocks of the FP32 solves, the last pair one block
 def test_half_precision_ir_on_dominant_matrix(gpu, prec, n):
     A = synth.dominant(n, seed=5)
     b = synth.rhs(n, seed=5)[:, 0]
