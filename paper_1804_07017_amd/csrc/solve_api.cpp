@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "../../include/lu.h"
 #include "../../include/lu_kernels.h"
@@ -91,6 +92,21 @@ int dev_amax(DeviceState* s, const double* v, int n, hipStream_t stream, double*
     return 0;
 }
 
+// ||u||_inf and ||v||_inf with one read-back (one synchronisation).
+int dev_amax2(DeviceState* s, const double* u, const double* v, int n, hipStream_t stream, double* out_u,
+              double* out_v) {
+    unsigned long long* w = reinterpret_cast<unsigned long long*>(s->ir_norms.ptr) + 8;
+    if (launch_fill_zero(w, 2 * sizeof(*w), stream)) return LU_ERR_HIP;
+    if (launch_amax(u, n, w, stream)) return LU_ERR_HIP;
+    if (launch_amax(v, n, w + 1, stream)) return LU_ERR_HIP;
+    unsigned long long h[2] = {0, 0};
+    LU_HIP(hipMemcpyAsync(h, w, sizeof h, hipMemcpyDeviceToHost, stream));
+    LU_HIP(hipStreamSynchronize(stream));
+    *out_u = bits_to_double(h[0]);
+    *out_v = bits_to_double(h[1]);
+    return 0;
+}
+
 // Outcome of a factorization enqueued on `stream` with the library's INFO
 // word: waits for it, returns LU_ERR_BARRIER if one of its panel barriers
 // timed out (the error words are cleared for the next call), else 0 with
@@ -130,17 +146,16 @@ int fp64_path(DeviceState* s, int n, int nrhs, const double* A, long long lda, c
     return read_err(s, stream);
 }
 
-// HPL residual of column c: ||A x - b|| / (eps (||A|| ||x|| + ||b||) n)
+// HPL residual of column c: ||A x - b|| / (eps (||A|| ||x|| + ||b||) n), with
+// ||b|| given (the caller has it from the input check)
 int hpl_resid(DeviceState* s, int n, const double* A, long long lda, const double* b, const double* x, double anorm,
-              hipStream_t stream, double* out) {
+              double bn, hipStream_t stream, double* out) {
     double* r = reinterpret_cast<double*>(s->ir_r.ptr);
     double* part = reinterpret_cast<double*>(s->partial.ptr);
     if (launch_residual(A, lda, n, x, b, r, part, kSplits, stream)) return LU_ERR_HIP;
-    double rn, xn, bn;
+    double rn, xn;
     int rc;
-    if ((rc = dev_amax(s, r, n, stream, &rn))) return rc;
-    if ((rc = dev_amax(s, x, n, stream, &xn))) return rc;
-    if ((rc = dev_amax(s, b, n, stream, &bn))) return rc;
+    if ((rc = dev_amax2(s, r, x, n, stream, &rn, &xn))) return rc;
     const double denom = kEps * (anorm * xn + bn) * (double)n;
     *out = denom > 0 ? rn / denom : (rn == 0 ? 0.0 : INFINITY);
     if (!std::isfinite(rn) || !std::isfinite(xn)) *out = NAN;
@@ -185,10 +200,10 @@ int solve_ir_impl(int n, int nrhs, const double* A, int lda, const double* B, in
     LU_HIP(hipStreamSynchronize(stream));
     const double anorm = bits_to_double(abits);
     if (!std::isfinite(anorm)) return LU_ERR_NONFINITE;
+    std::vector<double> bnorm(nrhs);
     for (int c = 0; c < nrhs; ++c) {
-        double bn;
-        if ((rc = dev_amax(s, B + (long long)c * ldb, n, stream, &bn))) return rc;
-        if (!std::isfinite(bn)) return LU_ERR_NONFINITE;
+        if ((rc = dev_amax(s, B + (long long)c * ldb, n, stream, &bnorm[c]))) return rc;
+        if (!std::isfinite(bnorm[c])) return LU_ERR_NONFINITE;
     }
 
     int iters_total = 0;
@@ -203,7 +218,8 @@ int solve_ir_impl(int n, int nrhs, const double* A, int lda, const double* B, in
         if (info == 0) {
             for (int c = 0; c < nrhs; ++c) {
                 double res;
-                if ((r = hpl_resid(s, n, A, lda, B + (long long)c * ldb, X + (long long)c * ldx, anorm, stream, &res)))
+                if ((r = hpl_resid(s, n, A, lda, B + (long long)c * ldb, X + (long long)c * ldx, anorm, bnorm[c],
+                                   stream, &res)))
                     return r;
                 worst = std::isnan(res) || std::isnan(worst) ? NAN : std::max(worst, res);
             }
@@ -229,8 +245,7 @@ int solve_ir_impl(int n, int nrhs, const double* A, int lda, const double* B, in
         double* x = X + (long long)c * ldx;
         double* r = reinterpret_cast<double*>(s->ir_r.ptr);
         if (launch_fill_zero(x, (size_t)n * sizeof(double), stream)) return LU_ERR_HIP;
-        double bn;
-        if ((rc = dev_amax(s, b, n, stream, &bn))) return rc;
+        const double bn = bnorm[c];
         double prev = INFINITY;
         int it = 0;
         for (;; ++it) {
@@ -238,7 +253,7 @@ int solve_ir_impl(int n, int nrhs, const double* A, int lda, const double* B, in
             const bool start = it == 0 && bn > 0.0;
             if (!start) {
                 double res;
-                if ((rc = hpl_resid(s, n, A, lda, b, x, anorm, stream, &res))) return rc;   // leaves r = b - A x
+                if ((rc = hpl_resid(s, n, A, lda, b, x, anorm, bn, stream, &res))) return rc;   // leaves r = b - A x
                 if (std::isnan(res)) { converged = false; break; }
                 if (res <= 16.0) { worst = std::max(worst, res); break; }
                 if (it >= max_iter || (it >= 2 && res >= prev)) { converged = false; break; }
