@@ -1,13 +1,15 @@
 // Solves with the packed LU factor (LAPACK getrs semantics: x = U^-1 L^-1 P b)
 // and the FP64 side of iterative refinement.
 //
-// Triangular solves are "sync-free": one work-group per 64-row block, launched
-// in block order.  Block r accumulates L(r, c) x(c) for every finished block
-// c < r as soon as c's ready flag shows the current epoch, then solves its
-// 64 x 64 diagonal block in one wave and publishes x(r) with a release store
-// of its flag.  A work-group only waits for lower-numbered blocks, which the
-// hardware dispatched before it, so the grid always makes progress; every wait
-// is bounded by a wall-clock limit that sets an error word instead of hanging.
+// Triangular solves are "sync-free": the rows are cut into 64-row blocks, each
+// with a ready flag, and work-groups are launched in block order (the LU
+// solves take two consecutive blocks per work-group, the Cholesky solves one).
+// A work-group accumulates L(r, c) x(c) for every finished block c before its
+// own as soon as c's flag shows the current epoch, then solves its diagonal
+// part in one wave and publishes its x values, then its flags.  A work-group
+// only waits for lower-numbered blocks, which the hardware dispatched before
+// it, so the grid always makes progress; every wait is bounded by a
+// wall-clock limit that sets an error word instead of hanging.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -69,7 +71,7 @@ struct Pair {
     static constexpr int acc = 512;                   // accumulating threads
     static constexpr int first = own_ctl ? kRB : 0;   // the first of them
     static constexpr int threads = first + acc;
-    static constexpr int groups = acc / kPR;
+    static constexpr int groups = acc / kPR;          // 4 (the partial sums of sum_parts)
     static constexpr int per = kPR / groups;          // columns per thread per finished pair
 };
 
@@ -99,10 +101,9 @@ __device__ __forceinline__ T ld_in(const T* a, long long lda, int r, int c, int 
     return a[min(r, n - 1) + (long long)min(c, n - 1) * lda];
 }
 
-template <typename T, int G>
-__device__ __forceinline__ T sum_parts(const T (&part)[G][kPR], int i) {
-    if constexpr (G == 2) return part[0][i] + part[1][i];
-    else return (part[0][i] + part[1][i]) + (part[2][i] + part[3][i]);
+template <typename T>
+__device__ __forceinline__ T sum_parts(const T (&part)[4][kPR], int i) {
+    return (part[0][i] + part[1][i]) + (part[2][i] + part[3][i]);
 }
 
 // kRB serial substitution steps of a wave: at step sc, the chain value c of
