@@ -160,11 +160,38 @@ def cholesky_leg(lu, n, reps, A0, A):
             raise RuntimeError("cholesky: status %d info %d" % (st, info))
     t = statistics.median(ts)
     gf = n ** 3 / 3.0 / (t * 1e-3) / 1e9
+    # one right-hand side with the last factor (chol_solve, potrs semantics):
+    # median over reps timed solves, each from the same b; HPL residual of the
+    # last against the pristine matrix (a device GEMV in FP64)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(8)
+    bvec = torch.empty(n, dtype=torch.float64, device=A.device).uniform_(-1.0, 1.0, generator=g)
+    x = torch.empty_like(bvec)
+    tss = []
+    for r in range(reps + 1):
+        with torch.cuda.stream(stream):
+            x.copy_(bvec)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            rc = lu.chol_solve(A, x, stream=stream)
+            e1.record(stream)
+        stream.synchronize()
+        if rc != 0:
+            raise RuntimeError("chol_solve returned %d" % rc)
+        if r:
+            tss.append(e0.elapsed_time(e1))
+    with torch.no_grad():
+        a_inf = 0.0
+        for c0 in range(0, n, 4096):
+            a_inf = max(a_inf, A0[c0:min(n, c0 + 4096), :].abs().sum(dim=1).max().item())
+        res = (A0 @ x - bvec).abs().max().item()
+        hpl = res / (2.0 ** -53 * (a_inf * x.abs().max().item() + bvec.abs().max().item()) * n)
     return {"workload": "FP64 Cholesky with look-ahead of an SPD n=%d matrix (symmetric uniform[-1,1) part, "
                         "diagonal = row absolute sum)" % n,
             "schedule": {"b": 256, "depth": 2, "panel_cus": 32}, "t_factor_ms": round(t, 3),
             "gflops": round(gf, 1), "flops": "n^3/3", "pct_fp64_peak": round(100 * gf / 1e3 / FP64_PEAK_TFLOPS, 2),
-            "runs": reps}
+            "t_solve_ms": round(statistics.median(tss), 3), "hpl_resid": hpl, "runs": reps}
 
 
 def qr_leg(lu, n, reps, A0, A):

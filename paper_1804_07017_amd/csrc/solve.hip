@@ -203,14 +203,18 @@ __device__ __forceinline__ void publish_pair(T* x, int n, int r0, T y0, T y1, in
     if (tid == 1 && 2 * w + 1 < nblk) xstore(&flags[2 * w + 1], epoch);
 }
 
-template <typename T>
-__global__ __launch_bounds__(Pair<T>::threads) void trsv_lower_unit_kernel(const T* __restrict__ LU, long long lda, int n,
-                                                                     T* __restrict__ x, int* flags, int epoch,
-                                                                     unsigned* err, long long limit) {
+// L y = b for a pair of blocks.  Unit: L has a unit diagonal (the LU factor).
+// Otherwise (a Cholesky factor) the pair's own part is solved as L' z = c with
+// L' = L D^-1 (each column divided by its diagonal entry, unit diagonal) and
+// then y = D^-1 z, which keeps the divisions off the serial chain.
+template <typename T, bool Unit>
+__device__ __forceinline__ void trsv_lower_pair(const T* __restrict__ LU, long long lda, int n, T* __restrict__ x,
+                                                int* flags, int epoch, unsigned* err, long long limit) {
     constexpr int kPThreads = Pair<T>::threads, kPG = Pair<T>::groups, kPPerT = Pair<T>::per;
     __shared__ T part[kPG][kPR];
-    __shared__ T La[kRB][kPR];     // La[s][i] = L(r0 + i, r0 + s): the first block's columns, all 128 rows
-    __shared__ T Lb[kRB][kRB];     // Lb[s][i] = L(r0 + 64 + i, r0 + 64 + s): the second block's diagonal
+    __shared__ T La[kRB][kPR];     // La[s][i] = L(r0 + i, r0 + s) (/ L(r0 + s, r0 + s)): the first block's columns
+    __shared__ T Lb[kRB][kRB];     // Lb[s][i] = L(r0 + 64 + i, r0 + 64 + s) (scaled alike): the second block's diagonal
+    __shared__ T dg[kPR];          // L(r0 + k, r0 + k) (not Unit)
     const int w = blockIdx.x;
     const int nblk = (n + kRB - 1) / kRB;
     const int r0 = w * kPR;
@@ -223,18 +227,28 @@ __global__ __launch_bounds__(Pair<T>::threads) void trsv_lower_unit_kernel(const
     const T b0 = x[min(r0 + tid % kRB, n - 1)];     // used only by wave 0, for rows inside the matrix
     const T b1 = x[min(r0 + kRB + tid % kRB, n - 1)];
     // the diagonal part does not depend on other blocks: stage it first
-    // (entries outside the matrix as zero)
+    // (entries outside the matrix as zero; not Unit, scaled by the column's
+    // diagonal entry, entries on or above the diagonal zero)
+    if constexpr (!Unit) {
+        if (tid < kPR) {
+            const T v = ld_in(LU, lda, r0 + tid, r0 + tid, n);
+            dg[tid] = (r0 + tid < n) ? v : T(0);
+        }
+        __syncthreads();
+    }
     if (acc_t) {
         for (int sc = g; sc < kRB; sc += kPG) {
             const T v = ld_in(LU, lda, row, r0 + sc, n);
-            La[sc][i] = (row < n && r0 + sc < n) ? v : T(0);
+            if constexpr (Unit) La[sc][i] = (row < n && r0 + sc < n) ? v : T(0);
+            else La[sc][i] = (row < n && i > sc) ? v / dg[sc] : T(0);
         }
     }
     for (int e = tid; e < kRB * kRB; e += kPThreads) {
         const int sc = e / kRB, ii = e % kRB;
         const int rr = r0 + kRB + ii, cc = r0 + kRB + sc;
         const T v = ld_in(LU, lda, rr, cc, n);
-        Lb[sc][ii] = (rr < n && cc < n) ? v : T(0);
+        if constexpr (Unit) Lb[sc][ii] = (rr < n && cc < n) ? v : T(0);
+        else Lb[sc][ii] = (rr < n && ii > sc) ? v / dg[kRB + sc] : T(0);
     }
     // this thread's columns of the finished pair p (inside the matrix, since
     // p < w; rows past n load row n - 1 and their sums are discarded).  The
@@ -271,8 +285,27 @@ __global__ __launch_bounds__(Pair<T>::threads) void trsv_lower_unit_kernel(const
         T none = T(0);
         chain_steps<T, false, true>(&La[0][0], kPR, 0, kRB, y0, y1);    // the first block's columns
         chain_steps<T, false, false>(&Lb[0][0], kRB, 0, 0, y1, none);   // the second block's diagonal
+        if constexpr (!Unit) {
+            y0 = (r0 + tid < n) ? y0 / dg[tid] : T(0);
+            y1 = (r0 + kRB + tid < n) ? y1 / dg[kRB + tid] : T(0);
+        }
     }
     publish_pair(x, n, r0, y0, y1, flags, w, nblk, epoch);
+}
+
+template <typename T>
+__global__ __launch_bounds__(Pair<T>::threads) void trsv_lower_unit_kernel(const T* __restrict__ LU, long long lda, int n,
+                                                                     T* __restrict__ x, int* flags, int epoch,
+                                                                     unsigned* err, long long limit) {
+    trsv_lower_pair<T, true>(LU, lda, n, x, flags, epoch, err, limit);
+}
+
+// Cholesky: L y = b with the non-unit lower factor
+template <typename T>
+__global__ __launch_bounds__(Pair<T>::threads) void trsv_chol_lower_kernel(const T* __restrict__ L, long long lda, int n,
+                                                                     T* __restrict__ x, int* flags, int epoch,
+                                                                     unsigned* err, long long limit) {
+    trsv_lower_pair<T, false>(L, lda, n, x, flags, epoch, err, limit);
 }
 
 template <typename T>
@@ -365,62 +398,6 @@ __global__ __launch_bounds__(Pair<T>::threads) void trsv_upper_kernel(const T* _
     publish_pair(x, n, r0, y0, y1, flags, w, nblk, epoch);
 }
 
-// Solves with a Cholesky factor (L lower, non-unit diagonal, A = L L^T).
-// L y = b: as trsv_lower_unit_kernel with the division by the diagonal.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void trsv_chol_lower_kernel(const T* __restrict__ L, long long lda, int n,
-                                                                    T* __restrict__ x, int* flags, int epoch,
-                                                                    unsigned* err, long long limit) {
-    __shared__ T part[4][kRB];
-    __shared__ T Ld[kRB][kRB + 1];
-    const int r = blockIdx.x;
-    const int tid = threadIdx.x, i = tid % kRB, g = tid / kRB;
-    const int row = r * kRB + i;
-    const int nb = min(kRB, n - r * kRB);
-    // this block's right-hand side, loaded before any wait (nothing else writes it)
-    const T b_row = (tid < kRB && row < n) ? x[row] : T(0);
-    for (int s = g; s < kRB; s += 4) Ld[s][i] = (row < n && s < nb) ? L[row + (long long)(r * kRB + s) * lda] : T(0);
-    constexpr int kPerT = kRB / 4;
-    auto load_l = [&](int cb, T (&lv)[kPerT]) {
-        const int j0 = cb * kRB;
-#pragma unroll
-        for (int u = 0; u < kPerT; ++u) lv[u] = (row < n) ? L[row + (long long)(j0 + g + 4 * u) * lda] : T(0);
-    };
-    T acc = T(0);
-    T lv[kPerT];
-    if (r > 0) load_l(0, lv);
-    for (int cb = 0; cb < r; ++cb) {
-        T ln[kPerT];
-        if (cb + 1 < r) load_l(cb + 1, ln);
-        if (wait_flag(&flags[cb], epoch, err, limit)) return;
-        if (row < n) {
-            const int j0 = cb * kRB;
-#pragma unroll
-            for (int u = 0; u < kPerT; ++u) acc += lv[u] * xload(&x[j0 + g + 4 * u]);
-        }
-        if (cb + 1 < r) {
-#pragma unroll
-            for (int u = 0; u < kPerT; ++u) lv[u] = ln[u];
-        }
-    }
-    part[g][i] = acc;
-    __syncthreads();
-    T y = T(0);
-    if (tid < kRB) {
-        y = (row < n) ? b_row - ((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) : T(0);
-        // unrolled and branch-free (LDS reads ahead of the serial chain)
-#pragma unroll
-        for (int s = 0; s < kRB; ++s) {
-            const bool live = s < nb;                  // steps past a ragged block's end change nothing
-            const T l = Ld[s][i];
-            y = (live && i == s) ? y / l : y;          // other lanes' quotients are dropped
-            const T xs = lane_t(y, s);                 // lane s's value (s is uniform)
-            y = (live && i > s) ? y - l * xs : y;
-        }
-    }
-    publish(x, row, y, tid < kRB && row < n, &flags[r], epoch);
-}
-
 // L^T x = y, bottom block first.  Element (i, j) of L^T is L[j + i*lda]: the
 // off-diagonal blocks are read along j (contiguous) into LDS, transposed.
 template <typename T>
@@ -428,7 +405,10 @@ __global__ __launch_bounds__(kThreads) void trsv_chol_upper_kernel(const T* __re
                                                                     T* __restrict__ x, int* flags, int epoch,
                                                                     unsigned* err, long long limit) {
     __shared__ T part[4][kRB];
-    __shared__ T Ud[kRB][kRB + 1];       // Ud[s][i] = L^T(i, s) = L(s, i), this block's diagonal part
+    // this block's diagonal part, solved as U' z = c with U' = U D^-1 (unit
+    // diagonal), U = L^T, then x = D^-1 z (the divisions off the serial chain)
+    __shared__ T Ud[kRB][kRB + 1];       // Ud[s][i] = L^T(i, s) / L(s, s) = L(s, i) / L(s, s), i < s
+    __shared__ T dg[kRB];                // L(r0 + i, r0 + i)
     __shared__ T S[kRB][kRB + 1];        // S[i][jj] = L^T(i, j0 + jj) of the block being applied
     const int nblk = (n + kRB - 1) / kRB;
     const int r = nblk - 1 - (int)blockIdx.x;
@@ -436,21 +416,27 @@ __global__ __launch_bounds__(kThreads) void trsv_chol_upper_kernel(const T* __re
     const int r0 = r * kRB;
     const int row = r0 + i;
     const int nb = min(kRB, n - r0);
-    // this block's right-hand side, loaded before any wait (nothing else writes it)
-    const T b_row = (tid < kRB && row < n) ? x[row] : T(0);
+    // this block's right-hand side, loaded before any wait (nothing else writes
+    // it); loads below are unconditional from clamped addresses (a conditional
+    // load compiles to a branch that waits for each round trip)
+    const T b_row = x[min(row, n - 1)];            // used only for rows inside the matrix
+    if (tid < kRB) {
+        const T v = ld_in(L, lda, row, row, n);
+        dg[i] = row < n ? v : T(0);
+    }
+    __syncthreads();
     // coalesced along the rows of L: thread (jj = tid % 64) reads L(r0 + jj, r0 + ii)
     for (int ii = g; ii < kRB; ii += 4) {
-        const bool ok = i < nb && ii < nb && i >= ii;
-        Ud[i][ii] = ok ? L[(r0 + i) + (long long)(r0 + ii) * lda] : T(0);
+        const T v = ld_in(L, lda, r0 + i, r0 + ii, n);
+        Ud[i][ii] = (i < nb && ii < i) ? v / dg[i] : T(0);
     }
     constexpr int kPerT = kRB / 4;
-    auto load_s = [&](int cb, T (&v)[kPerT]) {   // v[u] = L(j0 + i, r0 + g + 4u): row j0+i of L
+    // v[u] = L(j0 + i, r0 + g + 4u): row j0+i of L; entries outside the
+    // matrix are never used (their x or their row is out of range)
+    auto load_s = [&](int cb, T (&v)[kPerT]) {
         const int j0 = cb * kRB;
 #pragma unroll
-        for (int u = 0; u < kPerT; ++u) {
-            const int ii = g + 4 * u;
-            v[u] = (j0 + i < n && ii < nb) ? L[(j0 + i) + (long long)(r0 + ii) * lda] : T(0);
-        }
+        for (int u = 0; u < kPerT; ++u) v[u] = ld_in(L, lda, j0 + i, r0 + g + 4 * u, n);
     };
     T acc = T(0);
     T sv[kPerT];
@@ -480,14 +466,10 @@ __global__ __launch_bounds__(kThreads) void trsv_chol_upper_kernel(const T* __re
     T y = T(0);
     if (tid < kRB) {
         y = (row < n) ? b_row - ((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) : T(0);
-#pragma unroll
-        for (int s = kRB - 1; s >= 0; --s) {
-            const bool live = s < nb;                  // steps past a ragged block's end change nothing
-            const T u = Ud[s][i];
-            y = (live && i == s) ? y / u : y;          // other lanes' quotients are dropped
-            const T xs = lane_t(y, s);
-            y = (live && i < s) ? y - u * xs : y;
-        }
+        // rows and columns past a ragged block's end hold zero and change nothing
+        T none = T(0);
+        chain_steps<T, true, false>(&Ud[0][0], kRB + 1, 0, 0, y, none);
+        y = (row < n) ? y / dg[i] : T(0);
     }
     publish(x, row, y, tid < kRB && row < n, &flags[r], epoch);
 }
@@ -675,8 +657,9 @@ int launch_trsv_chol(const T* L, long long lda, int n, T* x, int* flags, int epo
                      unsigned* err, long long spin_limit, hipStream_t stream) {
     if (n <= 0) return 0;
     const int nblk = (n + kRB - 1) / kRB;
-    hipLaunchKernelGGL((trsv_chol_lower_kernel<T>), dim3(nblk), dim3(kThreads), 0, stream, L, lda, n, x, flags,
-                       epoch_lower, err, spin_limit);
+    const int npair = (nblk + 1) / 2;
+    hipLaunchKernelGGL((trsv_chol_lower_kernel<T>), dim3(npair), dim3(Pair<T>::threads), 0, stream, L, lda, n, x,
+                       flags, epoch_lower, err, spin_limit);
     hipLaunchKernelGGL((trsv_chol_upper_kernel<T>), dim3(nblk), dim3(kThreads), 0, stream, L, lda, n, x, flags,
                        epoch_upper, err, spin_limit);
     return hipGetLastError() == hipSuccess ? 0 : -1;
