@@ -64,8 +64,10 @@ def test_not_positive_definite_info(gpu, bad):
     assert info == oinfo
 
 
+# the lower solve takes 64-row blocks two per work-group: 191 and 4160 give an
+# odd block count (a work-group with one block) past the first pair
 @pytest.mark.parametrize("n,nrhs,lda,ldb", [(1, 1, None, None), (37, 2, 40, 41), (1000, 1, None, None),
-                                            (1500, 3, 1503, 1500)])
+                                            (1500, 3, 1503, 1500), (191, 2, 193, None), (4160, 1, None, None)])
 def test_chol_solve_matches_oracle(gpu, n, nrhs, lda, ldb):
     import torch
     from scipy.linalg import solve_triangular
